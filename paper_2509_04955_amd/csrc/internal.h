@@ -1,0 +1,167 @@
+// Internal declarations shared by the host planner, the C ABI and the HIP
+// kernels of libqsim.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qsim.h"
+
+namespace qs {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+qs_status hip_fail(hipError_t e, const char *what);
+
+#define QS_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return qs::hip_fail(e_, #call); \
+    } while (0)
+
+#define QS_CHECK(cond, code, ...)          \
+    do {                                   \
+        if (!(cond)) {                     \
+            qs::set_error(__VA_ARGS__);    \
+            return (code);                 \
+        }                                  \
+    } while (0)
+
+// ------------------------------------------------------------- limits
+constexpr int kMaxQubits = 40;
+constexpr int kMaxTile = 14;          // tile qubits t (complex64: 2^14 * 8 B = 128 KiB LDS)
+constexpr int kMaxTile128 = 13;       // complex128 tile limit (128 KiB)
+constexpr int kMaxK = 6;              // widest fused block
+constexpr int kMaxK128 = 5;
+constexpr int kTileThreads = 256;     // threads per tile workgroup
+
+// ------------------------------------------------------ device records
+// One fused block as the tile kernel sees it.
+struct BlockDev {
+    int32_t k;          // width
+    int32_t mfma;       // 1: complex64 block applied with MFMA (A operand pre-swizzled)
+    int32_t mat_off;    // offset (reals) of the matrix in the plan's pool
+    int32_t pad;
+    int32_t pos[kMaxK]; // tile positions (ascending) of the block's qubits
+    int32_t pad2[2];
+};
+static_assert(sizeof(BlockDev) == 48, "BlockDev layout");
+
+// Launch arguments of one pass (passed by value).
+struct PassArgs {
+    int32_t t;          // tile qubits
+    int32_t c;          // tile positions 0..c-1 are global qubits 0..c-1
+    int32_t nblocks;
+    int32_t block0;     // first block in the plan's block table
+    int32_t hi[kMaxTile];   // global qubit of tile position c + j (ascending)
+    int32_t apply_scale;    // multiply amplitudes by *scale on load
+    int32_t want_norm;      // write FP64 sum |a|^2 partial per tile
+};
+
+// --------------------------------------------------------------- state
+struct Prof;
+}  // namespace qs
+
+struct qs_state_s {
+    int n = 0;
+    qs_dtype dtype = QS_C64;
+    void *amp = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // FP64 norm chain: slot[0] = norm of last pass, slot[1] = scale to apply next.
+    double *d_slots = nullptr;
+    double *d_partials = nullptr;
+    size_t partials_cap = 0;
+    bool scale_pending = false;
+};
+
+namespace qs {
+
+// Host gate after validation: full matrix with local bit j <-> q[j].
+struct HGate {
+    int kind = 0;
+    int nq = 0;
+    int q[8] = {0};
+    double p[4] = {0, 0, 0, 0};
+    std::vector<cd> m;   // 2^nq x 2^nq row-major
+};
+
+struct HBlock {
+    std::vector<int> qubits;     // ascending
+    std::vector<int64_t> members;
+    std::vector<cd> U;           // 2^k x 2^k, local bit j <-> qubits[j]
+};
+
+struct HPass {
+    int t = 0, c = 0;
+    std::vector<int> tile;       // ascending global qubits, size t
+    int64_t block0 = 0, nblocks = 0;
+};
+
+}  // namespace qs
+
+struct qs_plan_s {
+    int n = 0;
+    qs_contract_opts opts{};
+    std::vector<qs::HGate> gates;
+    std::vector<qs::HBlock> blocks;
+    std::vector<qs::HPass> passes;
+    // device copies (built on first use per dtype)
+    int dev_ready[2] = {0, 0};
+    qs::BlockDev *d_blocks[2] = {nullptr, nullptr};
+    void *d_pool[2] = {nullptr, nullptr};
+    std::vector<qs::BlockDev> h_blocks[2];
+    ~qs_plan_s();
+};
+
+namespace qs {
+
+// ------------------------------------------------------------- host API
+// gates.cpp
+qs_status make_gate(const qs_gate &g, int n, HGate &out);
+// planner.cpp
+qs_status build_plan(qs_plan_s &p);
+void block_matrix(const std::vector<HGate> &gates, HBlock &b);
+qs_status plan_upload(qs_plan_s &p, qs_dtype dt);
+void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
+                 std::vector<HPass> &out);
+int default_tile(qs_dtype dt);
+// learned.cpp
+bool costmodel_loaded();
+double costmodel_predict_host(const float *feat);
+int pass_features(int n, int t, const std::vector<HBlock> &blocks, int64_t b0, int64_t nb, float *out);
+constexpr int kNumFeatures = 12;
+constexpr int kH1 = 64, kH2 = 64;
+constexpr int kNumWeights = kH1 * kNumFeatures + kH1 + kH2 * kH1 + kH2 + kH2 + 1;
+
+// ------------------------------------------------------- kernel launch
+// kernels_plain.hip
+struct Mat2 { double re[4], im[4]; };
+qs_status launch_plain(qs_state_s &s, const HGate &g);
+qs_status launch_scale(qs_state_s &s, const double *d_scale);
+qs_status launch_set_basis(qs_state_s &s, uint64_t index);
+qs_status launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
+// kernels_tile.hip
+qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &pass, int64_t pass_index, bool scale_in,
+                      bool want_norm);
+qs_status launch_norm_reduce(qs_state_s &s, uint64_t nparts, double *d_out_slots);
+qs_status launch_norm_full(qs_state_s &s, double *d_out_slots);
+qs_status ensure_partials(qs_state_s &s, size_t count);
+// kernels_expect.hip
+qs_status launch_expect(qs_state_s &s, const uint64_t *d_x, const uint64_t *d_z, size_t n_terms,
+                        double *d_parts, size_t parts_per_term, double *d_terms);
+size_t expect_parts_per_term(int n);
+
+// ------------------------------------------------------------ profiling
+bool prof_on();
+void prof_begin(hipStream_t st, int cls, double bytes, double flops);
+void prof_end(hipStream_t st);
+
+}  // namespace qs

@@ -1,0 +1,223 @@
+// Host planner: dependency-aware gate contraction (Section 3.4) and the
+// packing of fused blocks into streamed tile passes.
+//
+// DAG.  Gates that share a qubit (controls included) are ordered by program
+// order; gates with no path between them commute (Section 3.4).  The DAG is
+// never materialised: `last[q]` (the block holding the most recent gate on
+// qubit q) carries exactly the information the merge needs.
+//
+// Merge.  The paper merges greedily without fixing the rule; this library's
+// fixed-width greedy rule (width k_max) is: for gate g with qubit set Q,
+// f = max_{q in Q} last[q]; g joins the lowest block j >= max(f, 1) with
+// |Q_j u Q| <= k_max, else a new block.  Blocks after f hold no qubit of Q, so
+// for j > f the test is |Q_j| + |Q| <= k_max; a segment tree over block widths
+// finds that j in O(log blocks).  Block products compose the member gates in
+// program order (Kronecker embedding of each gate into the block's qubits, the
+// same-qubit product M2 M1 and the controlled merge being special cases).
+//
+// Passes.  Consecutive blocks are packed into one pass while the union of
+// their qubits with the always-present low qubits {0..c-1} stays within t
+// qubits; a pass is one read and one write of the state (one tile kernel).
+#include <algorithm>
+#include <cstring>
+#include <limits>
+#include <stdexcept>
+
+#include "internal.h"
+
+namespace qs {
+
+int default_tile(qs_dtype dt) { return dt == QS_C128 ? 12 : 13; }
+
+namespace {
+
+// Segment tree over block widths: first index > f whose width <= s.
+struct MinTree {
+    int size = 1;
+    std::vector<int> v;
+    explicit MinTree(size_t cap) {
+        while ((size_t)size < cap + 1) size <<= 1;
+        v.assign(2 * size, std::numeric_limits<int>::max());
+    }
+    void set(int i, int val) {
+        i += size;
+        v[i] = val;
+        for (i >>= 1; i; i >>= 1) v[i] = std::min(v[2 * i], v[2 * i + 1]);
+    }
+    // smallest index >= lo with value <= s, or -1
+    int first_le(int lo, int s) const { return find(1, 0, size, lo, s); }
+    int find(int node, int l, int r, int lo, int s) const {
+        if (r <= lo || v[node] > s) return -1;
+        if (r - l == 1) return l;
+        int m = (l + r) / 2;
+        int a = find(2 * node, l, m, lo, s);
+        return a >= 0 ? a : find(2 * node + 1, m, r, lo, s);
+    }
+};
+
+void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks) {
+    blocks.clear();
+    std::vector<int> last(n, 0);                 // 1-based block index, 0 = none
+    std::vector<uint64_t> qmask;                 // qubit mask per block
+    std::vector<int> width;
+    MinTree tree(gates.size() + 1);
+    for (size_t gi = 0; gi < gates.size(); ++gi) {
+        const HGate &g = gates[gi];
+        uint64_t gm = 0;
+        int f = 0;
+        for (int j = 0; j < g.nq; ++j) {
+            gm |= 1ull << g.q[j];
+            f = std::max(f, last[g.q[j]]);
+        }
+        const int w = g.nq;
+        int j = -1;  // 1-based
+        if (w <= kmax) {
+            if (f >= 1 && __builtin_popcountll(qmask[f - 1] | gm) <= kmax) {
+                j = f;
+            } else {
+                int idx = tree.first_le(std::max(f + 1, 1), kmax - w);  // tree index = 1-based block id
+                if (idx >= 1 && idx <= (int)blocks.size()) j = idx;
+            }
+        }
+        if (j < 0) {
+            blocks.emplace_back();
+            qmask.push_back(0);
+            width.push_back(0);
+            j = (int)blocks.size();
+        }
+        blocks[j - 1].members.push_back((int64_t)gi);
+        qmask[j - 1] |= gm;
+        width[j - 1] = __builtin_popcountll(qmask[j - 1]);
+        tree.set(j, width[j - 1]);
+        for (int q = 0; q < g.nq; ++q) last[g.q[q]] = j;
+    }
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        blocks[b].qubits.clear();
+        for (int q = 0; q < 64; ++q)
+            if ((qmask[b] >> q) & 1) blocks[b].qubits.push_back(q);
+    }
+}
+
+}  // namespace
+
+// U_B = G_m ... G_1 with each gate embedded into the block's qubits.
+void block_matrix(const std::vector<HGate> &gates, HBlock &b) {
+    const int k = (int)b.qubits.size();
+    const int d = 1 << k;
+    b.U.assign((size_t)d * d, cd(0, 0));
+    for (int i = 0; i < d; ++i) b.U[(size_t)i * d + i] = 1;
+    std::vector<cd> tmp;
+    for (int64_t gi : b.members) {
+        const HGate &g = gates[gi];
+        int lp[8];
+        for (int j = 0; j < g.nq; ++j)
+            lp[j] = (int)(std::find(b.qubits.begin(), b.qubits.end(), g.q[j]) - b.qubits.begin());
+        const int gd = 1 << g.nq;
+        int gmask = 0;
+        for (int j = 0; j < g.nq; ++j) gmask |= 1 << lp[j];
+        std::vector<int> off(gd);
+        for (int a = 0; a < gd; ++a) {
+            int o = 0;
+            for (int j = 0; j < g.nq; ++j)
+                if ((a >> j) & 1) o |= 1 << lp[j];
+            off[a] = o;
+        }
+        tmp.assign(gd, cd(0, 0));
+        // left-multiply: every column of U is a vector the gate acts on
+        for (int col = 0; col < d; ++col) {
+            for (int base = 0; base < d; ++base) {
+                if (base & gmask) continue;
+                for (int a = 0; a < gd; ++a) {
+                    cd acc = 0;
+                    for (int c2 = 0; c2 < gd; ++c2)
+                        acc += g.m[(size_t)a * gd + c2] * b.U[(size_t)(base | off[c2]) * d + col];
+                    tmp[a] = acc;
+                }
+                for (int a = 0; a < gd; ++a) b.U[(size_t)(base | off[a]) * d + col] = tmp[a];
+            }
+        }
+    }
+}
+
+void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
+                 std::vector<HPass> &out) {
+    out.clear();
+    const int n = p.n;
+    t = std::min(t, n);
+    c = std::min(c, t);
+    const uint64_t low = c >= 64 ? ~0ull : ((1ull << c) - 1);
+    uint64_t cur = low;
+    HPass ps;
+    ps.block0 = 0;
+    auto close = [&](int64_t end) {
+        ps.nblocks = end - ps.block0;
+        // fill the tile up to t qubits with the lowest unused qubits
+        uint64_t m = cur;
+        for (int q = 0; q < n && __builtin_popcountll(m) < t; ++q) m |= 1ull << q;
+        ps.t = t;
+        ps.tile.clear();
+        for (int q = 0; q < n; ++q)
+            if ((m >> q) & 1) ps.tile.push_back(q);
+        int cc = 0;
+        while (cc < (int)ps.tile.size() && ps.tile[cc] == cc) ++cc;
+        ps.c = cc;
+        // the planner sizes c so that every pass holds exactly t qubits and qubit 0
+        if ((int)ps.tile.size() != t || cc < 1) throw std::logic_error("pass tile invariant broken");
+        out.push_back(ps);
+    };
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        uint64_t bm = 0;
+        for (int q : blocks[b].qubits) bm |= 1ull << q;
+        if (__builtin_popcountll(cur | bm) > t) {
+            close((int64_t)b);
+            ps = HPass();
+            ps.block0 = (int64_t)b;
+            cur = low;
+        }
+        cur |= bm;
+    }
+    if (!blocks.empty()) close((int64_t)blocks.size());
+}
+
+qs_status build_plan(qs_plan_s &p) {
+    qs_contract_opts &o = p.opts;
+    const qs_dtype dt = o.dtype == QS_C128 ? QS_C128 : QS_C64;
+    const int kcap = dt == QS_C128 ? kMaxK128 : kMaxK;
+    if (o.k_max == 0) o.k_max = 5;
+    QS_CHECK(o.k_max >= 1 && o.k_max <= kcap, QS_EINVAL, "k_max %d outside 1..%d", o.k_max, kcap);
+    if (o.tile_qubits == 0) o.tile_qubits = default_tile(dt);
+    const int tcap = dt == QS_C128 ? kMaxTile128 : kMaxTile;
+    QS_CHECK(o.tile_qubits >= 2 && o.tile_qubits <= tcap, QS_EINVAL, "tile_qubits %d outside 2..%d",
+             o.tile_qubits, tcap);
+    if (o.low_qubits == 0) o.low_qubits = std::min(6, o.tile_qubits);
+    QS_CHECK(o.low_qubits >= 1 && o.low_qubits <= o.tile_qubits, QS_EINVAL, "low_qubits %d invalid",
+             o.low_qubits);
+    const int t = std::min(o.tile_qubits, p.n);
+    // Every block (a gate wider than k_max is a block of its own) must fit in a
+    // tile next to at least one low qubit, so that qubit 0 is always in the
+    // tile and tiles start with a contiguous run.
+    int wmax = o.k_max;
+    for (const HGate &g : p.gates) wmax = std::max(wmax, g.nq);
+    if (t < p.n)
+        QS_CHECK(std::min(wmax, p.n) <= t - 1, QS_EINVAL,
+                 "blocks of width %d need a tile of at least %d qubits (got %d)", wmax, wmax + 1, t);
+    const int c = std::max(1, std::min(o.low_qubits, t - std::min(wmax, t)));
+
+    if (o.strategy == QS_STRATEGY_NONE) {
+        p.blocks.clear();
+        for (size_t gi = 0; gi < p.gates.size(); ++gi) {
+            HBlock b;
+            b.members.push_back((int64_t)gi);
+            for (int j = 0; j < p.gates[gi].nq; ++j) b.qubits.push_back(p.gates[gi].q[j]);
+            std::sort(b.qubits.begin(), b.qubits.end());
+            p.blocks.push_back(std::move(b));
+        }
+    } else {
+        greedy_blocks(p.gates, p.n, o.k_max, p.blocks);
+    }
+    for (HBlock &b : p.blocks) block_matrix(p.gates, b);
+    pack_passes(p, p.blocks, t, c, p.passes);
+    return QS_OK;
+}
+
+}  // namespace qs

@@ -1,0 +1,179 @@
+"""Host-side checks of the C-ABI library (no GPU needed): every declared
+symbol is exported, argument errors come back as status codes, and the host
+planner (Section 3.4 contraction) agrees with the oracle's rule and block
+products."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qsynth
+from oracle import greedy
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2509_04955_amd import qsim
+
+    qsim.lib()
+    return qsim
+
+
+def test_every_declared_symbol_is_exported(Q):
+    with open(os.path.join(ROOT, "include", "qsim.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"^\s*(?:qs_status|const char \*|int)\s*(qs_\w+)\s*\(", text, re.M))
+    assert len(declared) >= 30
+    L = Q.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared <= set(Q.exported_symbols())
+
+
+def test_gate_struct_layout(Q):
+    import ctypes
+
+    assert ctypes.sizeof(Q.qs_gate) == 80
+    assert ctypes.sizeof(Q.qs_contract_opts) == 32
+
+
+def _plan(Q, c, **kw):
+    gl = Q.GateList(c)
+    return Q.qs_contract(c.n, gl, Q.opts(**kw)), gl
+
+
+@pytest.mark.parametrize("k_max", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_greedy_membership_matches_oracle(Q, k_max, seed):
+    """Block membership is integer work: it must equal the oracle's rule
+    exactly, block by block."""
+    c = qsynth.random_circuit(11, 200, seed=seed)
+    plan, _ = _plan(Q, c, k_max=k_max, tile_qubits=11)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        ref = greedy.greedy_fw(c.gates, k_max)
+        assert info.n_blocks == len(ref)
+        for b, members in enumerate(ref):
+            qs, _, mem = Q.qs_plan_block(plan, b, with_matrix=False)
+            assert mem == members
+            assert qs == greedy.block_qubits(c.gates, members)
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("k_max", [2, 4, 5])
+def test_block_products_match_oracle(Q, oracle, k_max):
+    """FP64 block matrices agree with the oracle's own composition, and the
+    blocks applied in order reproduce the circuit (plan checker)."""
+    n = 10
+    c = qsynth.random_circuit(n, 150, seed=7, max_dense=3)
+    plan, _ = _plan(Q, c, k_max=k_max, tile_qubits=10)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        qls, mats, blocks = [], [], []
+        for b in range(info.n_blocks):
+            qs, U, mem = Q.qs_plan_block(plan, b)
+            ref = greedy.block_matrix(c.gates, mem)
+            assert np.max(np.abs(U - ref)) < 1e-13
+            qls.append(qs)
+            mats.append(U)
+            blocks.append(mem)
+        greedy.check_order(c.gates, blocks)
+        psi0 = qsynth.random_state(n, seed=3)
+        ref = oracle.run(c, psi0.copy())
+        got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
+        assert np.max(np.abs(got - ref)) < 1e-12
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("t,c", [(8, 3), (10, 6), (13, 6)])
+def test_passes_cover_blocks(Q, t, c):
+    circ, _ = qsynth.ucc(24, n_exp=40, seed=4)
+    plan, _ = _plan(Q, circ, k_max=5, tile_qubits=t, low_qubits=c)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        nxt = 0
+        for i in range(info.n_passes):
+            tt, tile, fb, nb = Q.qs_plan_pass(plan, i)
+            assert tt == t and len(tile) == t and list(tile) == sorted(set(tile))
+            assert set(range(min(c, t - 5))) <= set(tile)
+            assert fb == nxt and nb >= 1
+            nxt += nb
+            for b in range(fb, fb + nb):
+                qs, _, _ = Q.qs_plan_block(plan, b, with_matrix=False)
+                assert set(qs) <= set(tile)
+        assert nxt == info.n_blocks
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("k_max,t", [(1, 6), (2, 6), (5, 6), (3, 4)])
+def test_pass_tiles_hold_wide_gates(Q, k_max, t):
+    """Gates wider than k_max (two-qubit gates at k_max = 1) are blocks of
+    their own; every pass tile must still hold t qubits including qubit 0."""
+    c = qsynth.random_circuit(12, 150, seed=k_max, max_dense=2)
+    plan, _ = _plan(Q, c, k_max=k_max, tile_qubits=t)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        for i in range(info.n_passes):
+            tt, tile, fb, nb = Q.qs_plan_pass(plan, i)
+            assert len(tile) == t and 0 in tile
+            for b in range(fb, fb + nb):
+                assert set(Q.qs_plan_block(plan, b, with_matrix=False)[0]) <= set(tile)
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+def test_block_wider_than_tile_rejected(Q):
+    c = qsynth.random_circuit(14, 50, seed=1)
+    with pytest.raises(Q.QsimError) as ei:
+        _plan(Q, c, k_max=5, tile_qubits=5)
+    assert ei.value.status == Q.QS_EINVAL
+
+
+def test_strategy_none_is_one_block_per_gate(Q):
+    c = qsynth.random_circuit(8, 50, seed=1)
+    plan, _ = _plan(Q, c, strategy=Q.STRATEGY_NONE, tile_qubits=8)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        assert info.n_blocks == 50
+        for b in range(50):
+            assert Q.qs_plan_block(plan, b, with_matrix=False)[2] == [b]
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("bad", [
+    ("h", (12,)), ("cx", (3, 3)), ("cx", (1,)), ("u3", (-1,)),
+])
+def test_invalid_gates_rejected(Q, bad):
+    c = qsynth.Circuit(12).add("h", (0,)).add(bad[0], bad[1], (0.1, 0.2, 0.3)[: qsynth.N_PARAMS.get(bad[0], 0)])
+    with pytest.raises(Q.QsimError) as ei:
+        _plan(Q, c)
+    assert ei.value.status == Q.QS_EINVAL
+    assert "gate 1" in str(ei.value)
+
+
+def test_bad_options_rejected(Q):
+    c = qsynth.ghz(8)
+    for kw in ({"k_max": 7}, {"tile_qubits": 15}, {"k_max": 6, "dtype": Q.QS_C128}):
+        with pytest.raises(Q.QsimError):
+            _plan(Q, c, **kw)
+
+
+def test_compression_on_paper_style_circuit(Q):
+    """HEA-like circuit (Section 4.1): greedy contraction removes most gates
+    (the paper reports 52-63 % average compression)."""
+    c = qsynth.hea(20, layers=5, seed=(9, 0))
+    plan, _ = _plan(Q, c, k_max=5)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        ratio = (info.n_gates - info.n_blocks) / info.n_gates
+        assert ratio > 0.5
+        assert info.max_k <= 5
+    finally:
+        Q.qs_plan_destroy(plan)

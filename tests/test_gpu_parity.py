@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances: complex128 paths max-abs <= 1e-12 (FP64 arithmetic, a few hundred
+gates of unit-norm amplitudes).  complex64 paths: each amplitude update adds
+a relative rounding error of about 2^-24 per gate or block; over the circuits
+here (<= a few thousand gates) the accumulated error stays below 1e-5 in
+max-abs and 1 - fidelity below 1e-6, which are the bounds written in the
+tests (the headline requirement is fidelity >= 1 - 1e-5)."""
+import math
+
+import numpy as np
+import pytest
+
+import qsynth
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+TOL64 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    from paper_2509_04955_amd import qsim
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    qsim.lib()
+    return qsim
+
+
+def run_plain(Q, c, dtype, psi0=None):
+    s = Q.State(c.n, dtype)
+    if psi0 is not None:
+        s.load(psi0)
+    s.apply_gates(Q.GateList(c))
+    out = s.amplitudes()
+    s.close()
+    return out
+
+
+def run_plan(Q, c, dtype, psi0=None, **kw):
+    kw.setdefault("dtype", dtype)
+    gl = Q.GateList(c)
+    plan = Q.qs_contract(c.n, gl, Q.opts(**kw))
+    s = Q.State(c.n, dtype)
+    if psi0 is not None:
+        s.load(psi0)
+    s.apply_plan(plan)
+    out = s.amplitudes()
+    nrm = s.norm()
+    s.close()
+    Q.qs_plan_destroy(plan)
+    return out, nrm
+
+
+def test_device_is_gfx950(Q):
+    cu, lds, arch = Q.qs_device_query()
+    assert arch.startswith("gfx950"), arch
+    assert cu >= 1 and lds >= 65536
+
+
+def test_plain_c128_random_12q(Q, oracle):
+    """12-qubit random circuit, 20 layers of H/RZ plus 6 CNOTs, complex128,
+    gate-by-gate: max-abs <= 1e-12 against the oracle."""
+    c = qsynth.plain_random(12, 20, 6, seed=1)
+    ref = oracle.run(c)
+    got = run_plain(Q, c, Q.QS_C128)
+    assert oracle.max_abs(ref, got) <= TOL128
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL64), (1, TOL128)])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 9])
+def test_plain_every_kind_every_qubit(Q, oracle, dtype, tol, n):
+    rng = np.random.default_rng(n)
+    c = qsynth.Circuit(n)
+    for q in range(n):
+        for name in qsynth.ONE_QUBIT:
+            c.add(name, (q,), tuple(rng.random() * 6 for _ in range(qsynth.N_PARAMS.get(name, 0))))
+    if n >= 2:
+        for a in range(n):
+            for b in range(n):
+                if a != b:
+                    for name in qsynth.TWO_QUBIT:
+                        c.add(name, (a, b), tuple(rng.random() * 6 for _ in range(qsynth.N_PARAMS.get(name, 0))))
+    psi0 = qsynth.random_state(n, seed=n)
+    ref = oracle.run(c, psi0.copy())
+    got = run_plain(Q, c, dtype, psi0)
+    assert oracle.max_abs(ref, got) <= tol * max(1, len(c) / 100)
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL64), (1, TOL128)])
+def test_plain_dense_gates(Q, oracle, dtype, tol):
+    n = 8
+    c = qsynth.random_circuit(n, 40, seed=3, kinds=["h", "cx"], max_dense=5 if dtype == 1 else 6)
+    psi0 = qsynth.random_state(n, seed=2)
+    ref = oracle.run(c, psi0.copy())
+    got = run_plain(Q, c, dtype, psi0)
+    assert oracle.max_abs(ref, got) <= tol
+
+
+@pytest.mark.parametrize("k_max", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("t", [6, 9, 13])
+def test_fused_c64_random(Q, oracle, k_max, t):
+    """Fused tile passes, complex64: VALU blocks (k <= 3) and MFMA blocks
+    (k = 4, 5) over several tiles and ragged pass boundaries."""
+    n = 14
+    if k_max > t - 1:
+        pytest.skip("block wider than tile")
+    c = qsynth.random_circuit(n, 300, seed=10 + k_max, max_dense=2)
+    psi0 = qsynth.random_state(n, seed=5)
+    ref = oracle.run(c, psi0.copy())
+    got, nrm = run_plan(Q, c, Q.QS_C64, psi0, k_max=k_max, tile_qubits=t)
+    assert oracle.max_abs(ref, got) <= TOL64
+    assert 1 - oracle.fidelity(ref, got) <= 1e-6
+    assert abs(nrm - 1) <= 1e-6
+
+
+@pytest.mark.parametrize("k_max", [1, 3, 5])
+@pytest.mark.parametrize("t", [7, 12])
+def test_fused_c128_random(Q, oracle, k_max, t):
+    n = 13
+    c = qsynth.random_circuit(n, 250, seed=20 + k_max, max_dense=2)
+    psi0 = qsynth.random_state(n, seed=6)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, Q.QS_C128, psi0, k_max=k_max, tile_qubits=t)
+    assert oracle.max_abs(ref, got) <= TOL128
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_fused_k6_valu_and_wide_dense(Q, oracle, dtype):
+    n = 12
+    kmax = 6 if dtype == 0 else 5
+    c = qsynth.random_circuit(n, 120, seed=31, max_dense=kmax)
+    psi0 = qsynth.random_state(n, seed=7)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=kmax, tile_qubits=12)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
+@pytest.mark.parametrize("renorm", [0, 1])
+def test_renorm_chain(Q, oracle, renorm):
+    n = 16
+    c = qsynth.brickwork(n, depth=10, seed=2)
+    ref = oracle.run(c)
+    got, nrm = run_plan(Q, c, Q.QS_C64, None, k_max=5, renorm=renorm)
+    assert 1 - oracle.fidelity(ref, got) <= 1e-6
+    assert abs(nrm - 1) <= (1e-12 if renorm else 1e-5)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_tiny_states_fused(Q, oracle, n):
+    c = qsynth.random_circuit(n, 30, seed=n, max_dense=min(n, 3))
+    psi0 = qsynth.random_state(n, seed=n)
+    ref = oracle.run(c, psi0.copy())
+    for dtype, tol in ((0, TOL64), (1, TOL128)):
+        got, _ = run_plan(Q, c, dtype, psi0, k_max=min(n, 3))
+        assert oracle.max_abs(ref, got) <= tol
+
+
+def test_strategy_none_and_greedy_agree(Q, oracle):
+    n = 15
+    c = qsynth.plain_random(n, 12, 7, seed=4)
+    ref = oracle.run(c)
+    a, _ = run_plan(Q, c, Q.QS_C128, None, strategy=Q.STRATEGY_NONE)
+    b, _ = run_plan(Q, c, Q.QS_C128, None, strategy=Q.STRATEGY_GREEDY, k_max=4)
+    assert oracle.max_abs(ref, a) <= TOL128
+    assert oracle.max_abs(ref, b) <= TOL128
+
+
+def test_ucc_against_closed_form(Q, oracle):
+    """UCC-style ansatz (Pauli exponentials compiled to CNOT ladders) at 20
+    qubits, complex64 fused, against the closed-form rotation oracle."""
+    n = 20
+    c, rots = qsynth.ucc(n, n_exp=60, seed=3)
+    ref = oracle.zero_state(n)
+    for x, z, th in rots:
+        oracle.pauli_rotation(ref, n, x, z, th)
+    got, nrm = run_plan(Q, c, Q.QS_C64, None, k_max=5)
+    assert 1 - oracle.fidelity(ref, got) <= 1e-6
+    assert oracle.max_abs(ref, got) <= TOL64
+    got128, _ = run_plan(Q, c, Q.QS_C128, None, k_max=5)
+    assert oracle.max_abs(ref, got128) <= TOL128
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, 1e-6), (1, 1e-12)])
+def test_expectation(Q, oracle, dtype, tol):
+    n = 14
+    c = qsynth.hea(n, layers=3, seed=(1, 1))
+    ham = qsynth.random_pauli_sum(n, 50, seed=(2, 2))
+    ref_psi = oracle.run(c)
+    ref_terms = np.array([oracle.expect_pauli(ref_psi, n, int(x), int(z)).real for x, z in zip(ham.x, ham.z)])
+    ref_E = float(np.dot(ham.coeff, ref_terms))
+    gl = Q.GateList(c)
+    plan = Q.qs_contract(n, gl, Q.opts(dtype=dtype))
+    s = Q.State(n, dtype)
+    s.apply_plan(plan)
+    E, terms = s.expect(ham, with_terms=True)
+    s.close()
+    Q.qs_plan_destroy(plan)
+    assert np.max(np.abs(terms - ref_terms)) <= tol
+    assert abs(E - ref_E) <= tol * 10
+
+
+def test_expectation_special_cases(Q, oracle):
+    n = 9
+    s = Q.State(n, Q.QS_C128)
+    s.set_basis(0)
+    x = np.array([0, 1, 0b101, 0], dtype=np.uint64)
+    z = np.array([0, 0, 0b101, 0b110], dtype=np.uint64)
+    E, terms = Q.qs_expect_pauli_sum(s.handle, x, z, np.ones(4), with_terms=True)
+    assert np.allclose(terms, [1, 0, 0, 1], atol=1e-15)
+    s.close()
+
+
+def test_errors_leave_state_unchanged(Q):
+    n = 6
+    s = Q.State(n, Q.QS_C128)
+    s.set_basis(5)
+    bad = qsynth.Circuit(n).add("h", (0,)).add("cx", (2, 2))
+    with pytest.raises(Q.QsimError) as ei:
+        s.apply_gates(Q.GateList(bad))
+    assert ei.value.status == Q.QS_EINVAL
+    amps = s.amplitudes()
+    assert amps[5] == 1 and np.count_nonzero(amps) == 1
+    other = Q.qs_contract(7, Q.GateList(qsynth.ghz(7)))
+    with pytest.raises(Q.QsimError):
+        Q.qs_apply_plan(s.handle, other)
+    Q.qs_plan_destroy(other)
+    with pytest.raises(Q.QsimError):
+        Q.qs_state_set_basis(s.handle, 1 << n)
+    s.close()
+    with pytest.raises(Q.QsimError):
+        Q.qs_state_create(0, 0, None, None)
+
+
+def test_copy_kernel(Q):
+    import torch
+
+    a = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    Q.qs_copy(b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
