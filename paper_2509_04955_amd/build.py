@@ -32,7 +32,8 @@ SOURCES = [
     "mlp.hip",
     "autotune.cpp",
 ]
-HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(ROOT, "include", "qsim.h")]
+HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "tile_device.h"),
+           os.path.join(ROOT, "include", "qsim.h")]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 HIP_FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-fno-gpu-rdc"]

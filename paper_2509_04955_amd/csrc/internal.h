@@ -43,10 +43,17 @@ constexpr int kTileThreads = 256;     // threads per tile workgroup
 
 // ------------------------------------------------------ device records
 // One fused block as the tile kernel sees it.
+// Block kinds: how the tile kernel applies a block's matrix.
+enum : int32_t {
+    BK_DENSE = 0,   // vector ALU, full 2^k x 2^k complex matrix
+    BK_MFMA = 1,    // complex64, k = 4 or 5: MFMA with a pre-swizzled A operand
+    BK_MONO = 2,    // monomial (one nonzero per column): y[dest(c)] = u_c x[c]
+};
+
 struct BlockDev {
     int32_t k;          // width
-    int32_t mfma;       // 1: complex64 block applied with MFMA (A operand pre-swizzled)
-    int32_t mat_off;    // offset (reals) of the matrix in the plan's pool
+    int32_t kind;       // BK_*
+    int32_t mat_off;    // offset (reals) of the matrix data in the plan's pool
     int32_t pad;
     int32_t pos[kMaxK]; // tile positions (ascending) of the block's qubits
     int32_t pad2[2];
@@ -118,6 +125,7 @@ struct qs_plan_s {
     qs::BlockDev *d_blocks[2] = {nullptr, nullptr};
     void *d_pool[2] = {nullptr, nullptr};
     std::vector<qs::BlockDev> h_blocks[2];
+    std::vector<uint8_t> pass_wide[2];  // pass needs the wide kernel variant
     ~qs_plan_s();
 };
 

@@ -27,234 +27,100 @@
 #include <cstdlib>
 #include <cstring>
 
-#include "internal.h"
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
+#include "tile_device.h"
 
 namespace qs {
 
 namespace {
 
-constexpr int TT = kTileThreads;
 constexpr uint32_t kMaxTileGrid = 1u << 20;
+using namespace tiledev;
 
-__device__ __forceinline__ uint32_t ins0_32(uint32_t x, int p) {
-    const uint32_t lo = x & ((1u << p) - 1);
-    return ((x - lo) << 1) | lo;
-}
-__device__ __forceinline__ uint64_t ins0_64(uint64_t x, int p) {
-    const uint64_t lo = x & ((1ull << p) - 1);
-    return ((x - lo) << 1) | lo;
-}
+// Amplitude vectors each lane prefetches for the next tile while the current
+// tile is being processed (16-byte vectors: 2 complex64 or 1 complex128).
+constexpr int kPrefetch = 8;
 
-// global offset (in amplitudes, relative to the tile base) of tile index li
-__device__ __forceinline__ uint64_t tile_offset(uint32_t li, const PassArgs &pa) {
-    uint64_t off = li & ((1u << pa.c) - 1);
-    const uint32_t h = li >> pa.c;
-    const int nh = pa.t - pa.c;
-#pragma unroll
-    for (int j = 0; j < kMaxTile; ++j)
-        if (j < nh && ((h >> j) & 1)) off |= 1ull << pa.hi[j];
-    return off;
-}
-
-__device__ __forceinline__ uint64_t tile_base(uint64_t tile, const PassArgs &pa) {
-    uint64_t b = tile << pa.c;
-    const int nh = pa.t - pa.c;
-#pragma unroll
-    for (int j = 0; j < kMaxTile; ++j)
-        if (j < nh) b = ins0_64(b, pa.hi[j]);
-    return b;
-}
-
-template <typename R>
-struct AmpOf;
-template <>
-struct AmpOf<float> {
-    using A = float2;
-};
-template <>
-struct AmpOf<double> {
-    using A = double2;
-};
-
-// ---- vector-ALU block: one group of 2^K amplitudes per lane -------------
-template <int K, typename R>
-__device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                           const R *__restrict__ U) {
-    using A = typename AmpOf<R>::A;
-    constexpr int D = 1 << K;
-    int pos[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
-    uint32_t off[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if ((r >> j) & 1) o |= 1u << pos[j];
-        off[r] = o;
-    }
-    const uint32_t G = 1u << (T - K);
-    for (uint32_t g = threadIdx.x; g < G; g += TT) {
-        uint32_t b = g;
-#pragma unroll
-        for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-        A v[D];
-#pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = tile[b + off[r]];
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            R yr = 0, yi = 0;
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                const R ur = U[2 * (r * D + c)], ui = U[2 * (r * D + c) + 1];
-                yr = fma(ur, v[c].x, yr);
-                yr = fma(-ui, v[c].y, yr);
-                yi = fma(ur, v[c].y, yi);
-                yi = fma(ui, v[c].x, yi);
-            }
-            A y;
-            y.x = yr;
-            y.y = yi;
-            tile[b + off[r]] = y;
-        }
-    }
-}
-
-// ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
-// Lane l of a wave: g = l / 16 selects the K-slice of each 16x16x4 step and the
-// output row quad, j = l % 16 the tile column.  Step s feeds B row (s/2)*4 + g
-// (real part for even s, imaginary for odd s); outputs land as complete
-// complex numbers Y[16h + 4g + q] (Re in M-tile h, Im in M-tile MT/2 + h).
-template <int K>
-__device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *bd, const float *__restrict__ Asw) {
-    constexpr int D = 1 << K;
-    constexpr int MT = 2 * D / 16;
-    constexpr int S = 2 * D / 4;
-    constexpr int NB = D / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int gq = lane >> 4, jc = lane & 15;
-    int pos[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
-    float a[MT][S];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int s = 0; s < S; ++s) a[mt][s] = Asw[(mt * S + s) * 64 + lane];
-    auto deposit = [&](int r) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if ((r >> j) & 1) o |= 1u << pos[j];
-        return o;
-    };
-    uint32_t offB[NB];
-#pragma unroll
-    for (int m = 0; m < NB; ++m) offB[m] = deposit(4 * m + gq);
-    uint32_t offC[MT / 2][4];
-#pragma unroll
-    for (int h = 0; h < MT / 2; ++h)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) offC[h][q] = deposit(16 * h + 4 * gq + q);
-    const uint32_t nchunks = (1u << (T - K)) / 16;
-    for (uint32_t ch = wave; ch < nchunks; ch += TT / 64) {
-        uint32_t cb = ch * 16 + jc;
-#pragma unroll
-        for (int j = 0; j < K; ++j) cb = ins0_32(cb, pos[j]);
-        float2 bv[NB];
-#pragma unroll
-        for (int m = 0; m < NB; ++m) bv[m] = tile[cb + offB[m]];
-        floatx4 acc[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float b = (s & 1) ? bv[s >> 1].y : bv[s >> 1].x;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][s], b, acc[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int h = 0; h < MT / 2; ++h)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tile[cb + offC[h][q]] = make_float2(acc[h][q], acc[MT / 2 + h][q]);
-    }
-}
-
-// ---- the pass kernel ------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(TT) void k_tile_pass(typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa,
+template <typename R, bool WIDE>
+__global__ __launch_bounds__(TT, (sizeof(R) == 4 && !WIDE) ? 2 : 1) void k_tile_pass(typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa,
                                                   const BlockDev *__restrict__ blocks, const R *__restrict__ pool,
                                                   const double *__restrict__ scale_in, double *__restrict__ partials) {
     using A = typename AmpOf<R>::A;
+    constexpr bool F32 = sizeof(R) == 4;
+    constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *tile = reinterpret_cast<A *>(smem_raw);
     __shared__ double red[TT / 64];
     const int T = pa.t;
     const uint32_t tsize = 1u << T;
+    const uint32_t nvec = tsize / APV;                  // 16-byte vectors per tile
     const R sc = pa.apply_scale ? (R)(*scale_in) : (R)1;
-    for (uint64_t tileid = blockIdx.x; tileid < ntiles; tileid += gridDim.x) {
-        const uint64_t base = tile_base(tileid, pa);
-        // ---- load (scaled) ----
-        if constexpr (sizeof(R) == 4) {
-            for (uint32_t li = threadIdx.x * 2; li < tsize; li += TT * 2) {
-                const uint64_t gidx = base | tile_offset(li, pa);
-                float4 v = *reinterpret_cast<const float4 *>(psi + gidx);
-                v.x *= sc;
-                v.y *= sc;
-                v.z *= sc;
-                v.w *= sc;
-                *reinterpret_cast<float4 *>(tile + li) = v;
-            }
+    float4 pre[kPrefetch];
+
+    auto gload = [&](uint64_t base, uint32_t vi) -> float4 {
+        const uint32_t li = vi * APV;
+        return *reinterpret_cast<const float4 *>(psi + (base | tile_offset(li, pa)));
+    };
+    auto lds_put = [&](uint32_t vi, float4 v) {
+        const uint32_t li = vi * APV;
+        if constexpr (F32) {
+            v.x *= sc;
+            v.y *= sc;
+            v.z *= sc;
+            v.w *= sc;
+            *reinterpret_cast<float4 *>(tile + sw(li)) = v;
         } else {
-            for (uint32_t li = threadIdx.x; li < tsize; li += TT) {
-                A v = psi[base | tile_offset(li, pa)];
-                v.x *= sc;
-                v.y *= sc;
-                tile[li] = v;
+            double2 d = *reinterpret_cast<double2 *>(&v);
+            d.x *= sc;
+            d.y *= sc;
+            tile[sw(li)] = d;
+        }
+    };
+    // prologue: prefetch the first tile
+    uint64_t tileid = blockIdx.x;
+    if (tileid < ntiles) {
+        const uint64_t base = tile_base(tileid, pa);
+#pragma unroll
+        for (int j = 0; j < kPrefetch; ++j) {
+            const uint32_t vi = threadIdx.x + j * TT;
+            if (vi < nvec) pre[j] = gload(base, vi);
+        }
+    }
+    for (; tileid < ntiles; tileid += gridDim.x) {
+        const uint64_t base = tile_base(tileid, pa);
+        // ---- prefetched part into LDS, the rest loaded directly ----
+#pragma unroll
+        for (int j = 0; j < kPrefetch; ++j) {
+            const uint32_t vi = threadIdx.x + j * TT;
+            if (vi < nvec) lds_put(vi, pre[j]);
+        }
+        for (uint32_t vi = threadIdx.x + kPrefetch * TT; vi < nvec; vi += TT) lds_put(vi, gload(base, vi));
+        __syncthreads();
+        // ---- start fetching the next tile ----
+        const uint64_t nxt = tileid + gridDim.x;
+        if (nxt < ntiles) {
+            const uint64_t nbase = tile_base(nxt, pa);
+#pragma unroll
+            for (int j = 0; j < kPrefetch; ++j) {
+                const uint32_t vi = threadIdx.x + j * TT;
+                if (vi < nvec) pre[j] = gload(nbase, vi);
             }
         }
-        __syncthreads();
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
-            const BlockDev *bd = blocks + pa.block0 + b;
-            const int k = bd->k;
-            const R *U = pool + bd->mat_off;
-            if constexpr (sizeof(R) == 4) {
-                if (bd->mfma) {
-                    if (k == 4) mfma_block<4>(tile, T, bd, U);
-                    else mfma_block<5>(tile, T, bd, U);
-                    __syncthreads();
-                    continue;
-                }
-            }
-            switch (k) {
-            case 1: valu_block<1, R>(tile, T, bd, U); break;
-            case 2: valu_block<2, R>(tile, T, bd, U); break;
-            case 3: valu_block<3, R>(tile, T, bd, U); break;
-            case 4: valu_block<4, R>(tile, T, bd, U); break;
-            case 5: valu_block<5, R>(tile, T, bd, U); break;
-            default:
-                if constexpr (sizeof(R) == 4) valu_block<6, R>(tile, T, bd, U);
-                break;
-            }
+            apply_block<R, WIDE>(tile, T, blocks + pa.block0 + b, pool);
             __syncthreads();
         }
         // ---- store + FP64 norm partial ----
         double nacc = 0.0;
-        if constexpr (sizeof(R) == 4) {
-            for (uint32_t li = threadIdx.x * 2; li < tsize; li += TT * 2) {
-                const float4 v = *reinterpret_cast<const float4 *>(tile + li);
-                *reinterpret_cast<float4 *>(psi + (base | tile_offset(li, pa))) = v;
+        for (uint32_t vi = threadIdx.x; vi < nvec; vi += TT) {
+            const uint32_t li = vi * APV;
+            const float4 v = *reinterpret_cast<const float4 *>(tile + sw(li));
+            *reinterpret_cast<float4 *>(psi + (base | tile_offset(li, pa))) = v;
+            if constexpr (F32) {
                 nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
-            }
-        } else {
-            for (uint32_t li = threadIdx.x; li < tsize; li += TT) {
-                const A v = tile[li];
-                psi[base | tile_offset(li, pa)] = v;
-                nacc += v.x * v.x + v.y * v.y;
+            } else {
+                const double2 d = *reinterpret_cast<const double2 *>(&v);
+                nacc += d.x * d.x + d.y * d.y;
             }
         }
         if (pa.want_norm) {
@@ -310,11 +176,11 @@ __global__ __launch_bounds__(256) void k_norm_parts(const A *__restrict__ psi, u
     if (threadIdx.x == 0) parts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-template <typename R>
+template <typename R, bool WIDE>
 void set_lds_limit(size_t bytes) {
     static size_t done = 0;
     if (bytes > done) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile_pass<R>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile_pass<R, WIDE>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         done = bytes;
     }
@@ -347,6 +213,92 @@ void swizzle_mfma(const std::vector<cd> &U, int k, std::vector<float> &out) {
             }
 }
 
+// Structure of a block matrix: monomial (exactly one entry per column with
+// |u| > kZeroTol, entries below it being rounding residue of exact zeros of
+// the gate product) or dense.
+constexpr double kZeroTol = 1e-14;
+
+bool monomial(const std::vector<cd> &U, int D, std::vector<int> &dest) {
+    dest.assign(D, -1);
+    for (int c = 0; c < D; ++c)
+        for (int r = 0; r < D; ++r)
+            if (std::abs(U[(size_t)r * D + c]) > kZeroTol) {
+                if (dest[c] >= 0) return false;
+                dest[c] = r;
+            }
+    for (int c = 0; c < D; ++c)
+        if (dest[c] < 0) return false;
+    return true;
+}
+
+bool structured_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_TILE_STRUCTURED");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v == 1;
+}
+
+template <typename R>
+void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<R> &pool, bool &wide) {
+    const int D = 1 << d.k;
+    std::vector<int> dest;
+    const bool f32 = dt == QS_C64;
+    if (structured_enabled() && monomial(blk.U, D, dest)) {
+        d.kind = BK_MONO;
+        d.mat_off = (int32_t)pool.size();
+        for (int c = 0; c < D; ++c) {
+            const cd u = blk.U[(size_t)dest[c] * D + c];
+            uint32_t o = 0;
+            for (int j = 0; j < d.k; ++j)
+                if ((dest[c] >> j) & 1) o |= 1u << d.pos[j];
+            pool.push_back((R)u.real());
+            pool.push_back((R)u.imag());
+            pool.push_back((R)sw(o));
+        }
+        if (d.k > 4) wide = true;
+    } else if (f32 && (d.k == 4 || d.k == 5) && t - d.k >= 4 && mfma_enabled()) {
+        d.kind = BK_MFMA;
+        d.mat_off = (int32_t)pool.size();
+        std::vector<float> sw;
+        swizzle_mfma(blk.U, d.k, sw);
+        for (float v : sw) pool.push_back((R)v);
+    } else {
+        d.kind = BK_DENSE;
+        d.mat_off = (int32_t)pool.size();
+        for (int i = 0; i < D * D; ++i) {
+            pool.push_back((R)blk.U[i].real());
+            pool.push_back((R)blk.U[i].imag());
+        }
+        if (d.k > 3) wide = true;
+    }
+    while (pool.size() % 4) pool.push_back((R)0);  // 16-byte aligned entries
+}
+
+// Workgroups of the tile kernel resident at once on the current device.
+uint64_t resident_groups(qs_dtype dt, bool wide, size_t lds) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    int per_cu = 0;
+    hipError_t e;
+    if (dt == QS_C64) {
+        if (wide) { set_lds_limit<float, true>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<float, true>, TT, lds); }
+        else { set_lds_limit<float, false>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<float, false>, TT, lds); }
+    } else {
+        if (wide) { set_lds_limit<double, true>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<double, true>, TT, lds); }
+        else { set_lds_limit<double, false>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<double, false>, TT, lds); }
+    }
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return (uint64_t)per_cu * (uint64_t)cus;
+}
+
 }  // namespace
 
 qs_status plan_upload(qs_plan_s &p, qs_dtype dt) {
@@ -355,7 +307,10 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt) {
     std::vector<BlockDev> hb(p.blocks.size());
     std::vector<float> pool32;
     std::vector<double> pool64;
-    for (const HPass &ps : p.passes) {
+    p.pass_wide[di].assign(p.passes.size(), 0);
+    for (size_t pi = 0; pi < p.passes.size(); ++pi) {
+        const HPass &ps = p.passes[pi];
+        bool wide = false;
         for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
             const HBlock &blk = p.blocks[b];
             BlockDev &d = hb[b];
@@ -365,28 +320,10 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt) {
                      "block width %d unsupported for this dtype", d.k);
             for (int j = 0; j < d.k; ++j)
                 d.pos[j] = (int)(std::find(ps.tile.begin(), ps.tile.end(), blk.qubits[j]) - ps.tile.begin());
-            const int D = 1 << d.k;
-            if (dt == QS_C64) {
-                d.mfma = (d.k == 4 || d.k == 5) && ps.t - d.k >= 4 && mfma_enabled();
-                d.mat_off = (int32_t)pool32.size();
-                if (d.mfma) {
-                    swizzle_mfma(blk.U, d.k, pool32);
-                } else {
-                    for (int i = 0; i < D * D; ++i) {
-                        pool32.push_back((float)blk.U[i].real());
-                        pool32.push_back((float)blk.U[i].imag());
-                    }
-                }
-                // keep every matrix 16-byte aligned
-                while (pool32.size() % 4) pool32.push_back(0.f);
-            } else {
-                d.mat_off = (int32_t)pool64.size();
-                for (int i = 0; i < D * D; ++i) {
-                    pool64.push_back(blk.U[i].real());
-                    pool64.push_back(blk.U[i].imag());
-                }
-            }
+            if (dt == QS_C64) push_block<float>(blk, d, ps.t, dt, pool32, wide);
+            else push_block<double>(blk, d, ps.t, dt, pool64, wide);
         }
+        p.pass_wide[di][pi] = wide ? 1 : 0;
     }
     p.h_blocks[di] = hb;
     const size_t bbytes = std::max<size_t>(1, hb.size()) * sizeof(BlockDev);
@@ -416,7 +353,6 @@ qs_status ensure_partials(qs_state_s &s, size_t count) {
 
 qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_t pass_index, bool scale_in,
                       bool want_norm) {
-    (void)pass_index;
     const int di = s.dtype == QS_C64 ? 0 : 1;
     PassArgs pa;
     std::memset(&pa, 0, sizeof pa);
@@ -432,23 +368,34 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
         qs_status st = ensure_partials(s, ntiles);
         if (st != QS_OK) return st;
     }
-    const dim3 grid((unsigned)std::min<uint64_t>(ntiles, kMaxTileGrid));
+    // persistent grid: as many workgroups as fit on the device at once, each
+    // walking tiles blockIdx.x, blockIdx.x + grid, ... with the next tile's
+    // loads in flight while the current one is processed
+    const bool wide = p.pass_wide[di][pass_index] != 0;
     const size_t amp = s.dtype == QS_C64 ? 8 : 16;
     const size_t lds = amp << ps.t;
+    const uint64_t resident = resident_groups(s.dtype, wide, lds);
+    const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
     const double S = std::ldexp((double)amp, s.n);
     double flops = 0;
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b)
-        flops += 8.0 * std::ldexp(1.0, (int)p.blocks[b].qubits.size()) * std::ldexp(1.0, s.n);
+        flops += (p.h_blocks[di][b].kind == BK_MONO ? 6.0 : 8.0 * std::ldexp(1.0, p.h_blocks[di][b].k)) *
+                 std::ldexp(1.0, s.n);
     prof_begin(s.stream, QS_PROF_TILE, 2 * S, flops);
+#define QS_LAUNCH_TILE(R, A, W)                                                                                   \
+    do {                                                                                                          \
+        set_lds_limit<R, W>(lds);                                                                                 \
+        hipLaunchKernelGGL((k_tile_pass<R, W>), grid, dim3(TT), lds, s.stream, (A *)s.amp, ntiles, pa,            \
+                           p.d_blocks[di], (const R *)p.d_pool[di], s.d_slots + 1, s.d_partials);                 \
+    } while (0)
     if (s.dtype == QS_C64) {
-        set_lds_limit<float>(lds);
-        hipLaunchKernelGGL(k_tile_pass<float>, grid, dim3(TT), lds, s.stream, (float2 *)s.amp, ntiles, pa,
-                           p.d_blocks[di], (const float *)p.d_pool[di], s.d_slots + 1, s.d_partials);
+        if (wide) QS_LAUNCH_TILE(float, float2, true);
+        else QS_LAUNCH_TILE(float, float2, false);
     } else {
-        set_lds_limit<double>(lds);
-        hipLaunchKernelGGL(k_tile_pass<double>, grid, dim3(TT), lds, s.stream, (double2 *)s.amp, ntiles, pa,
-                           p.d_blocks[di], (const double *)p.d_pool[di], s.d_slots + 1, s.d_partials);
+        if (wide) QS_LAUNCH_TILE(double, double2, true);
+        else QS_LAUNCH_TILE(double, double2, false);
     }
+#undef QS_LAUNCH_TILE
     prof_end(s.stream);
     QS_HIP(hipGetLastError());
     return QS_OK;

@@ -140,6 +140,23 @@ def test_fused_k6_valu_and_wide_dense(Q, oracle, dtype):
     assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("k_max", [1, 2, 3, 4, 5, 6])
+def test_fused_monomial_blocks(Q, oracle, dtype, k_max):
+    """Circuits of permutation and phase gates only (CNOT, CZ, SWAP, X, Z, S,
+    T, RZ, CP): every fused block is monomial and takes the gather-and-phase
+    path, up to the widest block (k = 6 complex64, 5 complex128)."""
+    if dtype == 1 and k_max > 5:
+        pytest.skip("complex128 blocks stop at k = 5")
+    n = 13
+    c = qsynth.random_circuit(n, 300, seed=40 + k_max,
+                              kinds=["cx", "cz", "swap", "x", "z", "s", "t", "rz", "cp"])
+    psi0 = qsynth.random_state(n, seed=8)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=k_max, tile_qubits=12)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
 @pytest.mark.parametrize("renorm", [0, 1])
 def test_renorm_chain(Q, oracle, renorm):
     n = 16
