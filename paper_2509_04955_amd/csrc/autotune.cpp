@@ -1,2 +1,118 @@
+// Autotuner: picks the fusion width k_max and tile size t for a circuit by
+// running candidate plans on the device and keeping the fastest.
+//
+// Candidates are k_max in 2..5 crossed with t in {11, 12, 13} (capped by n and
+// by the dtype's LDS limit).  Each candidate's plan runs on a scratch state
+// once to warm up and is then timed with hipEvents; circuits longer than
+// kTunePrefix gates are tuned on their first kTunePrefix gates (the passes of a
+// long circuit repeat the same structure).  Results are cached per
+// (n, dtype, strategy, gate structure) for the life of the process.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "internal.h"
-extern "C" qs_status qs_autotune(int, qs_dtype, const qs_gate *, size_t, const qs_contract_opts *, qs_contract_opts *) { return QS_EUNSUPPORTED; }
+
+namespace {
+
+constexpr size_t kTunePrefix = 4096;
+
+uint64_t structure_hash(const qs_gate *g, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    for (size_t i = 0; i < n; ++i) {
+        mix((uint64_t)g[i].kind);
+        mix((uint64_t)g[i].nq);
+        for (int j = 0; j < g[i].nq && j < 8; ++j) mix((uint64_t)g[i].qubits[j]);
+    }
+    return h;
+}
+
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, uint64_t>, qs_contract_opts> g_cache;
+
+}  // namespace
+
+extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, size_t n_gates,
+                                 const qs_contract_opts *base, qs_contract_opts *best) {
+    QS_CHECK(best != nullptr && (gates != nullptr || n_gates == 0), QS_EINVAL, "null argument");
+    QS_CHECK(n >= 1 && n <= 32, QS_EINVAL, "autotune supports 1 <= n <= 32 (got %d)", n);
+    qs_contract_opts b{};
+    if (base) b = *base;
+    else {
+        b.strategy = QS_STRATEGY_GREEDY;
+        b.renorm = 1;
+    }
+    b.dtype = dtype;
+    const size_t ng = std::min(n_gates, kTunePrefix);
+    const auto key = std::make_tuple(n, (int)dtype, (int)b.strategy, structure_hash(gates, ng));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            *best = it->second;
+            best->renorm = b.renorm;
+            return QS_OK;
+        }
+    }
+    const int kcap = dtype == QS_C128 ? 5 : 5;
+    const int tcap = dtype == QS_C128 ? 12 : 13;
+    int wmax = 1;
+    for (size_t i = 0; i < ng; ++i) wmax = std::max(wmax, (int)gates[i].nq);
+    std::vector<std::pair<int, int>> cand;
+    for (int k = 2; k <= kcap; ++k)
+        for (int t = 11; t <= tcap; ++t) {
+            const int tt = std::min(t, n);
+            const int kk = std::min(k, n);
+            if (tt < n && std::max(kk, wmax) > tt - 1) continue;
+            if (std::find(cand.begin(), cand.end(), std::make_pair(kk, tt)) == cand.end()) cand.push_back({kk, tt});
+        }
+    if (cand.empty()) cand.push_back({std::min(2, n), std::min(tcap, n)});
+    qs_state s = nullptr;
+    qs_status st = qs_state_create(n, dtype, nullptr, nullptr, &s);
+    if (st != QS_OK) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    qs_contract_opts win = b;
+    win.k_max = cand[0].first;
+    win.tile_qubits = cand[0].second;
+    for (auto [k, t] : cand) {
+        qs_contract_opts o = b;
+        o.k_max = k;
+        o.tile_qubits = t;
+        qs_plan p = nullptr;
+        st = qs_contract(n, gates, ng, &o, &p);
+        if (st != QS_OK) continue;  // candidate not valid for this circuit
+        float ms = 0;
+        bool ok = qs_state_set_basis(s, 0) == QS_OK && qs_apply_plan(s, p) == QS_OK;
+        if (ok) {
+            hipEventRecord(e0, nullptr);
+            ok = qs_apply_plan(s, p) == QS_OK;
+            hipEventRecord(e1, nullptr);
+            ok = ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        }
+        qs_plan_destroy(p);
+        if (ok && ms < best_ms) {
+            best_ms = ms;
+            win = o;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    qs_state_destroy(s);
+    QS_CHECK(best_ms < 1e30f, QS_EDEVICE, "autotune: no candidate plan could be timed");
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = win;
+    }
+    *best = win;
+    return QS_OK;
+}

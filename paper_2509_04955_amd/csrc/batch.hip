@@ -1,9 +1,654 @@
-#include "internal.h"
-extern "C" {
-qs_status qs_batch_create(int, const int *, const qs_gate *const *, const size_t *, const uint64_t *const *,
-                          const uint64_t *const *, const double *const *, const size_t *, const qs_contract_opts *,
-                          void *, qs_batch *) { qs::set_error("batches not built yet"); return QS_EUNSUPPORTED; }
-qs_status qs_batch_destroy(qs_batch) { return QS_OK; }
-qs_status qs_batch_run(qs_batch, double *) { return QS_EUNSUPPORTED; }
-qs_status qs_batch_state_copy_out(qs_batch, int, double *) { return QS_EUNSUPPORTED; }
+// Batches of independent states run by one persistent kernel in a hipGraph.
+//
+// Each state (its own qubit count, circuit and Pauli-sum Hamiltonian) gets a
+// contraction plan; all passes of all states and all expectation work become
+// one work queue:
+//   * pass items (state s, pass p, tile i): the tile kernel's work for one tile;
+//   * energy items (state s, term group, pair chunk): Pauli expectation partials.
+// Items are ordered pass-major across states (all first passes, then all
+// second passes, ..., then the energy items), so an item only ever waits for
+// items earlier in the queue.  The grid never exceeds the resident workgroup
+// count, so every earlier item is held by a running workgroup and every wait
+// ends; a bounded spin (with an error flag) guarantees termination anyway.
+//
+// Synchronisation: a finished pass item releases its tile (device-scope fence,
+// then an atomic increment of the state's done counter); a dependent item
+// acquires it (atomic load until the counter reaches the tiles completed by
+// earlier passes, then a fence).  The renormalisation scale of pass p is the
+// fixed-order FP64 sum of pass p-1's tile partials, recomputed by every
+// consumer, so all of them see the same value.  Energies are reduced by a
+// second kernel in fixed order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "tile_device.h"
+
+namespace qs {
+const char *last_error();
+
+namespace {
+using namespace tiledev;
+
+constexpr int kPassItem = 0, kEnergyItem = 1;
+constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr uint64_t kPairsPerItem = 1ull << 16;
+
+struct Seg {
+    uint64_t first;   // first item index
+    uint64_t count;
+    int32_t state;
+    int32_t kind;
+    int32_t pass;     // pass index within the state (pass items)
+    int32_t pad;
+};
+
+struct PassDev {
+    PassArgs pa;
+    uint64_t ntiles;
+    const BlockDev *blocks;
+    const void *pool;
+    uint64_t need_done;      // tiles of this state completed by earlier passes
+    uint64_t part_off;       // this pass's partials (offset into the batch partial array)
+    uint64_t prev_part_off;  // previous pass's partials
+    uint32_t prev_nparts;    // 0 for the first pass
+    uint32_t pad;
+};
+
+struct StateDev {
+    void *amp;
+    int32_t n;
+    int32_t npasses;
+    uint64_t pass0;         // index of the state's first PassDev
+    uint64_t total_tiles;   // tile items over all passes
+    uint64_t last_part_off; // partials of the last pass (norm of the stored state)
+    uint32_t last_nparts;
+    uint32_t nterms;
+    uint64_t term0;         // first term in the batch term arrays
+    uint32_t terms_per_item;
+    uint32_t nchunks;
+    uint64_t epart0;        // first energy partial (nterms * nchunks of them)
+};
+
+__device__ __forceinline__ uint32_t atomic_load_acq(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Fixed-order FP64 sum over `count` doubles by the whole workgroup.
+__device__ double wg_sum(const double *v, uint32_t count, double *red) {
+    double s = 0;
+    for (uint32_t i = threadIdx.x; i < count; i += TT) s += v[i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < TT / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+template <typename R, bool WIDE>
+__device__ void run_tile(typename AmpOf<R>::A *psi, const PassDev &pd, uint64_t tileid, R sc,
+                         typename AmpOf<R>::A *tile, double *red, double *partial_out) {
+    using A = typename AmpOf<R>::A;
+    constexpr bool F32 = sizeof(R) == 4;
+    constexpr uint32_t APV = F32 ? 2 : 1;
+    const PassArgs &pa = pd.pa;
+    const uint32_t nvec = (1u << pa.t) / APV;
+    const uint64_t base = tile_base(tileid, pa);
+    for (uint32_t vi = threadIdx.x; vi < nvec; vi += TT) {
+        const uint32_t li = vi * APV;
+        float4 v = *reinterpret_cast<const float4 *>(psi + (base | tile_offset(li, pa)));
+        if constexpr (F32) {
+            v.x *= sc;
+            v.y *= sc;
+            v.z *= sc;
+            v.w *= sc;
+            *reinterpret_cast<float4 *>(tile + sw(li)) = v;
+        } else {
+            double2 d = *reinterpret_cast<double2 *>(&v);
+            d.x *= sc;
+            d.y *= sc;
+            tile[sw(li)] = d;
+        }
+    }
+    __syncthreads();
+    const R *pool = reinterpret_cast<const R *>(pd.pool);
+    for (int b = 0; b < pa.nblocks; ++b) {
+        apply_block<R, WIDE>(tile, pa.t, pd.blocks + pa.block0 + b, pool);
+        __syncthreads();
+    }
+    double nacc = 0;
+    for (uint32_t vi = threadIdx.x; vi < nvec; vi += TT) {
+        const uint32_t li = vi * APV;
+        const float4 v = *reinterpret_cast<const float4 *>(tile + sw(li));
+        *reinterpret_cast<float4 *>(psi + (base | tile_offset(li, pa))) = v;
+        if constexpr (F32) {
+            nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        } else {
+            const double2 d = *reinterpret_cast<const double2 *>(&v);
+            nacc += d.x * d.x + d.y * d.y;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nacc += __shfl_xor(nacc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+#pragma unroll
+        for (int w = 0; w < TT / 64; ++w) s += red[w];
+        *partial_out = s;
+    }
+}
+
+__device__ __forceinline__ uint64_t ins0(uint64_t x, int p) {
+    const uint64_t lo = x & ((1ull << p) - 1);
+    return ((x - lo) << 1) | lo;
+}
+
+// Re <psi|P|psi> restricted to pair indices [u0, u1) (x != 0) or amplitude
+// indices [u0, u1) (x == 0); same pairing as the single-state kernel.
+template <typename A>
+__device__ double pauli_partial(const A *psi, uint64_t x, uint64_t z, uint64_t u0, uint64_t u1) {
+    double s = 0;
+    if (x == 0) {
+        for (uint64_t j = u0 + threadIdx.x; j < u1; j += TT) {
+            const A a = psi[j];
+            const double m = (double)a.x * a.x + (double)a.y * a.y;
+            s += (__popcll(j & z) & 1) ? -m : m;
+        }
+        return s;
+    }
+    const int h = 63 - __clzll(x);
+    const int ny = __popcll(x & z) & 3;
+    for (uint64_t u = u0 + threadIdx.x; u < u1; u += TT) {
+        const uint64_t j = ins0(u, h), jp = j ^ x;
+        const A a = psi[j], b = psi[jp];
+        const double wr = (double)b.x * a.x + (double)b.y * a.y;
+        const double wi = (double)b.x * a.y - (double)b.y * a.x;
+        const double sj = (__popcll(j & z) & 1) ? -1.0 : 1.0;
+        const double sp = (__popcll(jp & z) & 1) ? -1.0 : 1.0;
+        switch (ny) {
+        case 0: s += (sj + sp) * wr; break;
+        case 1: s -= (sj - sp) * wi; break;
+        case 2: s -= (sj + sp) * wr; break;
+        default: s += (sj - sp) * wi; break;
+        }
+    }
+    return s;
+}
+
+template <typename R, bool WIDE>
+__global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int nsegs, uint64_t total_items,
+                                              const StateDev *__restrict__ states, const PassDev *__restrict__ passes,
+                                              const uint64_t *__restrict__ xs, const uint64_t *__restrict__ zs,
+                                              double *__restrict__ partials, double *__restrict__ eparts,
+                                              uint32_t *__restrict__ done, unsigned long long *__restrict__ queue,
+                                              uint32_t *__restrict__ error) {
+    using A = typename AmpOf<R>::A;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *tile = reinterpret_cast<A *>(smem_raw);
+    __shared__ double red[TT / 64];
+    __shared__ unsigned long long s_item;
+    __shared__ int s_ok;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1ull);
+        __syncthreads();
+        const uint64_t item = s_item;
+        __syncthreads();
+        if (item >= total_items) break;
+        int lo = 0, hi = nsegs - 1;  // last segment with first <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (segs[mid].first <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const Seg sg = segs[lo];
+        const StateDev st = states[sg.state];
+        const uint64_t local = item - sg.first;
+        uint64_t need;
+        const PassDev *pd = nullptr;
+        if (sg.kind == kPassItem) {
+            pd = passes + st.pass0 + sg.pass;
+            need = pd->need_done;
+        } else {
+            need = st.total_tiles;
+        }
+        // ---- acquire: wait for the items this one depends on ----
+        if (threadIdx.x == 0) {
+            uint32_t spins = 0;
+            int ok = 1;
+            while (atomic_load_acq(done + sg.state) < need) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit || __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    atomicOr(error, 1u);
+                    ok = 0;
+                    break;
+                }
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!s_ok) break;
+        __threadfence();
+        A *psi = reinterpret_cast<A *>(st.amp);
+        if (sg.kind == kPassItem) {
+            R sc = (R)1;
+            if (pd->prev_nparts) {
+                const double N = wg_sum(partials + pd->prev_part_off, pd->prev_nparts, red);
+                sc = (R)(N > 0 ? 1.0 / sqrt(N) : 1.0);
+            }
+            run_tile<R, WIDE>(psi, *pd, local, sc, tile, red, partials + pd->part_off + local);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                atomicAdd(done + sg.state, 1u);
+            }
+        } else {
+            // energy item: (term group, chunk)
+            const uint64_t npairs = (st.n >= 1) ? (1ull << (st.n - 1)) : 1;
+            const uint64_t chunk = local % st.nchunks;
+            const uint64_t tg = local / st.nchunks;
+            const uint64_t cl = npairs / st.nchunks;
+            for (uint32_t j = 0; j < st.terms_per_item; ++j) {
+                const uint64_t term = tg * st.terms_per_item + j;
+                if (term >= st.nterms) break;
+                const uint64_t x = xs[st.term0 + term], z = zs[st.term0 + term];
+                const uint64_t u0 = (x == 0 ? 2 : 1) * chunk * cl, u1 = u0 + (x == 0 ? 2 : 1) * cl;
+                double s = pauli_partial<A>(psi, x, z, u0, u1);
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+                if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double t = 0;
+#pragma unroll
+                    for (int w = 0; w < TT / 64; ++w) t += red[w];
+                    eparts[st.epart0 + term * st.nchunks + chunk] = t;
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// zero every state, then |0...0>; reset counters (a fill kernel: graph-safe)
+__global__ __launch_bounds__(256) void k_batch_reset(uint4 *__restrict__ amps, uint64_t words,
+                                                     uint32_t *__restrict__ done, int nstates,
+                                                     unsigned long long *__restrict__ queue,
+                                                     uint32_t *__restrict__ error) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += stride) amps[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < nstates; i += 256) done[i] = 0;
+        if (threadIdx.x == 0) {
+            *queue = 0;
+            *error = 0;
+        }
+    }
+}
+
+template <typename A>
+__global__ void k_batch_basis(const StateDev *__restrict__ states, int nstates) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nstates) {
+        A one;
+        one.x = 1;
+        one.y = 0;
+        reinterpret_cast<A *>(states[i].amp)[0] = one;
+    }
+}
+
+// one workgroup per state: fixed-order sums
+__global__ __launch_bounds__(256) void k_batch_energy(const StateDev *__restrict__ states,
+                                                      const double *__restrict__ coeff,
+                                                      const double *__restrict__ partials,
+                                                      const double *__restrict__ eparts, double *__restrict__ energies) {
+    __shared__ double red[4];
+    const StateDev st = states[blockIdx.x];
+    const double N = wg_sum(partials + st.last_part_off, st.last_nparts, red);
+    double e = 0;
+    for (uint32_t t = 0; t < st.nterms; ++t) {
+        const double v = wg_sum(eparts + st.epart0 + (uint64_t)t * st.nchunks, st.nchunks, red);
+        e += coeff[st.term0 + t] * v;
+    }
+    if (threadIdx.x == 0) energies[blockIdx.x] = e / N;
+}
+
+}  // namespace
+}  // namespace qs
+
+using namespace qs;
+
+struct qs_batch_s {
+    qs_dtype dtype = QS_C64;
+    hipStream_t stream = nullptr;
+    int nstates = 0;
+    std::vector<qs_plan_s *> plans;
+    std::vector<int> n;
+    std::vector<uint64_t> amp_off;  // bytes
+    void *d_amps = nullptr;
+    uint64_t amp_bytes = 0;
+    Seg *d_segs = nullptr;
+    int nsegs = 0;
+    uint64_t total_items = 0;
+    StateDev *d_states = nullptr;
+    PassDev *d_passes = nullptr;
+    uint64_t *d_x = nullptr, *d_z = nullptr;
+    double *d_coeff = nullptr, *d_partials = nullptr, *d_eparts = nullptr, *d_energy = nullptr;
+    uint32_t *d_done = nullptr, *d_error = nullptr;
+    unsigned long long *d_queue = nullptr;
+    bool wide = false;
+    size_t lds = 0;
+    unsigned grid = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~qs_batch_s() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        void *bufs[] = {d_amps, d_segs, d_states, d_passes, d_x, d_z, d_coeff, d_partials, d_eparts, d_energy,
+                        d_done, d_error, d_queue};
+        for (void *b : bufs)
+            if (b) hipFree(b);
+        for (qs_plan_s *p : plans) qs_plan_destroy(p);
+    }
+};
+
+namespace {
+
+template <typename T>
+qs_status upload(T **dst, const std::vector<T> &src) {
+    QS_HIP(hipMalloc((void **)dst, std::max<size_t>(1, src.size()) * sizeof(T)));
+    if (!src.empty()) QS_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return QS_OK;
+}
+
+template <typename R, bool WIDE>
+const void *batch_kernel() {
+    return reinterpret_cast<const void *>(&k_batch<R, WIDE>);
+}
+
+qs_status enqueue_batch(qs_batch_s &b, hipStream_t st) {
+    const uint64_t words = b.amp_bytes / 16;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1024), dim3(256), 0, st, (uint4 *)b.d_amps, words, b.d_done, b.nstates,
+                       b.d_queue, b.d_error);
+    const unsigned nb = (unsigned)((b.nstates + 255) / 256);
+    if (b.dtype == QS_C64)
+        hipLaunchKernelGGL(k_batch_basis<float2>, dim3(nb), dim3(256), 0, st, b.d_states, b.nstates);
+    else
+        hipLaunchKernelGGL(k_batch_basis<double2>, dim3(nb), dim3(256), 0, st, b.d_states, b.nstates);
+#define QS_BATCH(R, W)                                                                                        \
+    hipLaunchKernelGGL((k_batch<R, W>), dim3(b.grid), dim3(TT), b.lds, st, b.d_segs, b.nsegs, b.total_items,   \
+                       b.d_states, b.d_passes, b.d_x, b.d_z, b.d_partials, b.d_eparts, b.d_done, b.d_queue,   \
+                       b.d_error)
+    if (b.dtype == QS_C64) {
+        if (b.wide) QS_BATCH(float, true);
+        else QS_BATCH(float, false);
+    } else {
+        if (b.wide) QS_BATCH(double, true);
+        else QS_BATCH(double, false);
+    }
+#undef QS_BATCH
+    hipLaunchKernelGGL(k_batch_energy, dim3(b.nstates), dim3(256), 0, st, b.d_states, b.d_coeff, b.d_partials,
+                       b.d_eparts, b.d_energy);
+    QS_HIP(hipGetLastError());
+    return QS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *const *circuits, const size_t *n_gates,
+                          const uint64_t *const *x, const uint64_t *const *z, const double *const *coeff,
+                          const size_t *n_terms, const qs_contract_opts *opts, void *stream, qs_batch *out) {
+    QS_CHECK(out && n_qubits && circuits && n_gates && x && z && coeff && n_terms, QS_EINVAL, "null argument");
+    QS_CHECK(n_states >= 1 && n_states <= 65536, QS_EINVAL, "n_states %d outside 1..65536", n_states);
+    qs_contract_opts base{};
+    if (opts) base = *opts;
+    if (base.strategy == 0 && !opts) base.strategy = QS_STRATEGY_GREEDY;
+    if (!opts) base.renorm = 1;
+    const qs_dtype dt = base.dtype == QS_C128 ? QS_C128 : QS_C64;
+    for (int i = 0; i < n_states; ++i) {
+        QS_CHECK(n_qubits[i] >= 1 && n_qubits[i] <= 26, QS_EINVAL, "state %d: n=%d outside 1..26", i, n_qubits[i]);
+        QS_CHECK(n_terms[i] >= 1 && n_terms[i] <= (1u << 16), QS_EINVAL, "state %d: n_terms outside 1..65536", i);
+        const uint64_t lim = (1ull << n_qubits[i]) - 1;
+        for (size_t k = 0; k < n_terms[i]; ++k)
+            QS_CHECK((x[i][k] & ~lim) == 0 && (z[i][k] & ~lim) == 0, QS_EINVAL, "state %d term %zu out of range", i, k);
+    }
+    qs_batch_s *b = new (std::nothrow) qs_batch_s();
+    QS_CHECK(b != nullptr, QS_ENOMEM, "host allocation failed");
+    b->dtype = dt;
+    b->stream = (hipStream_t)stream;
+    b->nstates = n_states;
+    auto fail = [&](qs_status s) {
+        delete b;
+        return s;
+    };
+    // ---- plans (autotuned per qubit count when k_max or tile is 0) ----
+    std::map<int, qs_contract_opts> tuned;
+    for (int i = 0; i < n_states; ++i) {
+        qs_contract_opts o = base;
+        o.dtype = dt;
+        if (base.k_max == 0 || base.tile_qubits == 0) {
+            auto it = tuned.find(n_qubits[i]);
+            if (it == tuned.end()) {
+                qs_contract_opts best{};
+                qs_status st = qs_autotune(n_qubits[i], dt, circuits[i], n_gates[i], &o, &best);
+                if (st != QS_OK) return fail(st);
+                it = tuned.emplace(n_qubits[i], best).first;
+            }
+            o = it->second;
+        }
+        qs_plan p = nullptr;
+        qs_status st = qs_contract(n_qubits[i], circuits[i], n_gates[i], &o, &p);
+        if (st != QS_OK) {
+            std::string m = last_error();
+            set_error("state %d: %s", i, m.c_str());
+            return fail(st);
+        }
+        b->plans.push_back(p);
+        b->n.push_back(n_qubits[i]);
+        st = plan_upload(*p, dt);
+        if (st != QS_OK) return fail(st);
+    }
+    // ---- device layout ----
+    const size_t ab = dt == QS_C64 ? 8 : 16;
+    uint64_t off = 0;
+    for (int i = 0; i < n_states; ++i) {
+        b->amp_off.push_back(off);
+        off += ((ab << b->n[i]) + 255) / 256 * 256;
+    }
+    b->amp_bytes = off;
+    hipError_t e = hipMalloc(&b->d_amps, off);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMalloc(batch states)"));
+    std::vector<StateDev> sd(n_states);
+    std::vector<PassDev> pdv;
+    std::vector<uint64_t> hx, hz;
+    std::vector<double> hc;
+    uint64_t parts = 0, eparts = 0;
+    int maxt = 1;
+    size_t maxpasses = 0;
+    for (int i = 0; i < n_states; ++i) {
+        qs_plan_s &p = *b->plans[i];
+        StateDev &s = sd[i];
+        std::memset(&s, 0, sizeof s);
+        s.amp = (unsigned char *)b->d_amps + b->amp_off[i];
+        s.n = b->n[i];
+        s.npasses = (int)p.passes.size();
+        s.pass0 = pdv.size();
+        uint64_t done_before = 0, prev_off = 0;
+        uint32_t prev_n = 0;
+        const int di = dt == QS_C64 ? 0 : 1;
+        for (size_t pi = 0; pi < p.passes.size(); ++pi) {
+            const HPass &ps = p.passes[pi];
+            PassDev d;
+            std::memset(&d, 0, sizeof d);
+            d.pa.t = ps.t;
+            d.pa.c = ps.c;
+            d.pa.nblocks = (int32_t)ps.nblocks;
+            d.pa.block0 = (int32_t)ps.block0;
+            for (int j = 0; j < ps.t - ps.c; ++j) d.pa.hi[j] = ps.tile[ps.c + j];
+            d.pa.want_norm = 1;
+            d.ntiles = 1ull << (s.n - ps.t);
+            d.blocks = p.d_blocks[di];
+            d.pool = p.d_pool[di];
+            d.need_done = done_before;
+            d.part_off = parts;
+            d.prev_part_off = prev_off;
+            d.prev_nparts = prev_n;
+            prev_off = parts;
+            prev_n = (uint32_t)d.ntiles;
+            parts += d.ntiles;
+            done_before += d.ntiles;
+            maxt = std::max(maxt, ps.t);
+            if (p.pass_wide[di][pi]) b->wide = true;
+            pdv.push_back(d);
+        }
+        maxpasses = std::max(maxpasses, p.passes.size());
+        s.total_tiles = done_before;
+        s.last_part_off = prev_off;
+        s.last_nparts = prev_n;
+        s.nterms = (uint32_t)n_terms[i];
+        s.term0 = hx.size();
+        const uint64_t npairs = 1ull << (s.n - 1);
+        s.nchunks = (uint32_t)std::max<uint64_t>(1, npairs / kPairsPerItem);
+        s.terms_per_item = (uint32_t)std::max<uint64_t>(1, kPairsPerItem / npairs);
+        s.epart0 = eparts;
+        eparts += (uint64_t)s.nterms * s.nchunks;
+        for (size_t k = 0; k < n_terms[i]; ++k) {
+            hx.push_back(x[i][k]);
+            hz.push_back(z[i][k]);
+            hc.push_back(coeff[i][k]);
+        }
+    }
+    // an empty circuit still needs the norm of |0>: give such states one identity pass
+    for (int i = 0; i < n_states; ++i)
+        if (sd[i].npasses == 0) {
+            set_error("state %d has an empty circuit", i);
+            return fail(QS_EINVAL);
+        }
+    // ---- queue: pass-major over states, then energy items ----
+    std::vector<Seg> segs;
+    uint64_t item = 0;
+    for (size_t pi = 0; pi < maxpasses; ++pi)
+        for (int i = 0; i < n_states; ++i)
+            if ((int)pi < sd[i].npasses) {
+                Seg s{item, pdv[sd[i].pass0 + pi].ntiles, i, kPassItem, (int32_t)pi, 0};
+                segs.push_back(s);
+                item += s.count;
+            }
+    for (int i = 0; i < n_states; ++i) {
+        const uint64_t groups = (sd[i].nterms + sd[i].terms_per_item - 1) / sd[i].terms_per_item;
+        Seg s{item, groups * sd[i].nchunks, i, kEnergyItem, 0, 0};
+        segs.push_back(s);
+        item += s.count;
+    }
+    b->total_items = item;
+    b->nsegs = (int)segs.size();
+    qs_status st;
+    if ((st = upload(&b->d_segs, segs)) != QS_OK) return fail(st);
+    if ((st = upload(&b->d_states, sd)) != QS_OK) return fail(st);
+    if ((st = upload(&b->d_passes, pdv)) != QS_OK) return fail(st);
+    if ((st = upload(&b->d_x, hx)) != QS_OK) return fail(st);
+    if ((st = upload(&b->d_z, hz)) != QS_OK) return fail(st);
+    if ((st = upload(&b->d_coeff, hc)) != QS_OK) return fail(st);
+    e = hipMalloc(&b->d_partials, std::max<uint64_t>(1, parts) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&b->d_eparts, std::max<uint64_t>(1, eparts) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&b->d_energy, n_states * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&b->d_done, n_states * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&b->d_error, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&b->d_queue, sizeof(unsigned long long));
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMalloc(batch)"));
+    // ---- persistent grid: resident workgroups only ----
+    b->lds = ab << maxt;
+    const void *kern = dt == QS_C64 ? (b->wide ? batch_kernel<float, true>() : batch_kernel<float, false>())
+                                    : (b->wide ? batch_kernel<double, true>() : batch_kernel<double, false>());
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipFuncSetAttribute(batch)"));
+    int per_cu = 0, dev = 0;
+    hipDeviceProp_t prop;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT, b->lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail(hip_fail(e, "occupancy query"));
+    QS_CHECK(per_cu >= 1, QS_EDEVICE, "batch kernel cannot be resident");
+    b->grid = (unsigned)std::min<uint64_t>((uint64_t)per_cu * prop.multiProcessorCount, std::max<uint64_t>(1, item));
+    // ---- capture the whole batch in one graph ----
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_batch(*b, cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &b->graph);
+        if (st == QS_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+    } else {
+        st = hip_fail(e, "hipStreamBeginCapture");
+    }
+    hipStreamDestroy(cap);
+    if (st != QS_OK) return fail(st);
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipGraphInstantiate"));
+    *out = b;
+    return QS_OK;
+}
+
+qs_status qs_batch_destroy(qs_batch b) {
+    if (!b) return QS_OK;
+    hipStreamSynchronize(b->stream);
+    delete b;
+    return QS_OK;
+}
+
+qs_status qs_batch_run(qs_batch b, double *energies) {
+    QS_CHECK(b != nullptr, QS_EINVAL, "null batch");
+    QS_HIP(hipGraphLaunch(b->exec, b->stream));
+    uint32_t err = 0;
+    QS_HIP(hipMemcpyAsync(&err, b->d_error, sizeof err, hipMemcpyDeviceToHost, b->stream));
+    if (energies)
+        QS_HIP(hipMemcpyAsync(energies, b->d_energy, b->nstates * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    QS_HIP(hipStreamSynchronize(b->stream));
+    QS_CHECK(err == 0, QS_EDEVICE, "batch kernel: a dependency wait timed out");
+    return QS_OK;
+}
+
+qs_status qs_batch_state_copy_out(qs_batch b, int i, double *host) {
+    QS_CHECK(b && host, QS_EINVAL, "null argument");
+    QS_CHECK(i >= 0 && i < b->nstates, QS_EINVAL, "state index out of range");
+    QS_HIP(hipStreamSynchronize(b->stream));
+    const qs_plan_s &p = *b->plans[i];
+    (void)p;
+    const int n = b->n[i];
+    const uint64_t cnt = 1ull << n;
+    // the stored amplitudes carry the last pass's pending scale: read the partials back
+    double N = 0;
+    {
+        // norm of the stored state = fixed-order sum of the last pass's partials
+        StateDev sd;
+        QS_HIP(hipMemcpy(&sd, b->d_states + i, sizeof sd, hipMemcpyDeviceToHost));
+        std::vector<double> parts(sd.last_nparts);
+        QS_HIP(hipMemcpy(parts.data(), b->d_partials + sd.last_part_off, parts.size() * sizeof(double),
+                         hipMemcpyDeviceToHost));
+        for (double v : parts) N += v;
+    }
+    const double scale = N > 0 ? 1.0 / std::sqrt(N) : 1.0;
+    const unsigned char *src = (const unsigned char *)b->d_amps + b->amp_off[i];
+    if (b->dtype == QS_C64) {
+        std::vector<float> f(2 * cnt);
+        QS_HIP(hipMemcpy(f.data(), src, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (uint64_t k = 0; k < 2 * cnt; ++k) host[k] = f[k] * scale;
+    } else {
+        QS_HIP(hipMemcpy(host, src, 2 * cnt * sizeof(double), hipMemcpyDeviceToHost));
+        for (uint64_t k = 0; k < 2 * cnt; ++k) host[k] *= scale;
+    }
+    return QS_OK;
+}
+
+}  // extern "C"

@@ -138,16 +138,23 @@ qs_status make_gate(const qs_gate &g, int n, HGate &out);
 qs_status build_plan(qs_plan_s &p);
 void block_matrix(const std::vector<HGate> &gates, HBlock &b);
 qs_status plan_upload(qs_plan_s &p, qs_dtype dt);
+// kernels_tile.hip: how the tile kernel will apply a block (BK_*); dest gets
+// the monomial destinations when the block is monomial
+int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest);
 void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
                  std::vector<HPass> &out);
+void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks);
 int default_tile(qs_dtype dt);
-// learned.cpp
-bool costmodel_loaded();
-double costmodel_predict_host(const float *feat);
-int pass_features(int n, int t, const std::vector<HBlock> &blocks, int64_t b0, int64_t nb, float *out);
-constexpr int kNumFeatures = 12;
+// learned.cpp: features of one pass (kNumFeatures floats) and the learned
+// per-window partition
+constexpr int kNumFeatures = 14;
 constexpr int kH1 = 64, kH2 = 64;
 constexpr int kNumWeights = kH1 * kNumFeatures + kH1 + kH2 * kH1 + kH2 + kH2 + 1;
+void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock> &blocks, float *out);
+qs_status learned_partition(qs_plan_s &p, int t, int c);
+// mlp.hip: the active cost model
+bool costmodel_loaded();
+qs_status costmodel_predict_device(const float *features, int n_rows, float *out);
 
 // ------------------------------------------------------- kernel launch
 // kernels_plain.hip

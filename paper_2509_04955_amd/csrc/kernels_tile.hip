@@ -245,7 +245,8 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<
     const int D = 1 << d.k;
     std::vector<int> dest;
     const bool f32 = dt == QS_C64;
-    if (structured_enabled() && monomial(blk.U, D, dest)) {
+    const int kind = block_kind(blk, t, dt, &dest);
+    if (kind == BK_MONO) {
         d.kind = BK_MONO;
         d.mat_off = (int32_t)pool.size();
         for (int c = 0; c < D; ++c) {
@@ -258,7 +259,8 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<
             pool.push_back((R)sw(o));
         }
         if (d.k > 4) wide = true;
-    } else if (f32 && (d.k == 4 || d.k == 5) && t - d.k >= 4 && mfma_enabled()) {
+    } else if (kind == BK_MFMA) {
+        (void)f32;
         d.kind = BK_MFMA;
         d.mat_off = (int32_t)pool.size();
         std::vector<float> sw;
@@ -300,6 +302,14 @@ uint64_t resident_groups(qs_dtype dt, bool wide, size_t lds) {
 }
 
 }  // namespace
+
+int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest) {
+    const int k = (int)b.qubits.size();
+    std::vector<int> tmp;
+    if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp)) return BK_MONO;
+    if (dt == QS_C64 && (k == 4 || k == 5) && t - k >= 4 && mfma_enabled()) return BK_MFMA;
+    return BK_DENSE;
+}
 
 qs_status plan_upload(qs_plan_s &p, qs_dtype dt) {
     const int di = dt == QS_C64 ? 0 : 1;

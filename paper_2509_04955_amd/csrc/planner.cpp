@@ -55,6 +55,8 @@ struct MinTree {
     }
 };
 
+}  // namespace
+
 void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks) {
     blocks.clear();
     std::vector<int> last(n, 0);                 // 1-based block index, 0 = none
@@ -97,8 +99,6 @@ void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector
             if ((qmask[b] >> q) & 1) blocks[b].qubits.push_back(q);
     }
 }
-
-}  // namespace
 
 // U_B = G_m ... G_1 with each gate embedded into the block's qubits.
 void block_matrix(const std::vector<HGate> &gates, HBlock &b) {
@@ -212,6 +212,8 @@ qs_status build_plan(qs_plan_s &p) {
             std::sort(b.qubits.begin(), b.qubits.end());
             p.blocks.push_back(std::move(b));
         }
+    } else if (o.strategy == QS_STRATEGY_LEARNED && costmodel_loaded()) {
+        return learned_partition(p, t, c);
     } else {
         greedy_blocks(p.gates, p.n, o.k_max, p.blocks);
     }

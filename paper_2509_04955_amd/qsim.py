@@ -271,6 +271,57 @@ def qs_expect_pauli_sum(h, x, z, coeff, with_terms: bool = False):
     return (out.value, terms) if with_terms else out.value
 
 
+class Batch:
+    """A batch of states run by one persistent kernel in a hipGraph
+    (qs_batch_create / qs_batch_run)."""
+
+    def __init__(self, circuits, hams, o: qs_contract_opts | None = None, stream: int | None = None):
+        self.n = [c.n for c in circuits]
+        count = len(circuits)
+        self._gls = [GateList(c) for c in circuits]
+        self._x = [np.ascontiguousarray(h.x, dtype=np.uint64) for h in hams]
+        self._z = [np.ascontiguousarray(h.z, dtype=np.uint64) for h in hams]
+        self._c = [np.ascontiguousarray(h.coeff, dtype=np.float64) for h in hams]
+        nq = (ctypes.c_int * count)(*self.n)
+        circ = (ctypes.c_void_p * count)(*[g.ptr.value for g in self._gls])
+        ng = (ctypes.c_size_t * count)(*[g.count for g in self._gls])
+        xs = (ctypes.c_void_p * count)(*[a.ctypes.data for a in self._x])
+        zs = (ctypes.c_void_p * count)(*[a.ctypes.data for a in self._z])
+        cs = (ctypes.c_void_p * count)(*[a.ctypes.data for a in self._c])
+        nt = (ctypes.c_size_t * count)(*[len(a) for a in self._c])
+        self.handle = ctypes.c_void_p()
+        _check(lib().qs_batch_create(count, nq, circ, ng, xs, zs, cs, nt,
+                                     ctypes.byref(o) if o is not None else None, stream, ctypes.byref(self.handle)))
+
+    def run(self) -> np.ndarray:
+        out = np.zeros(len(self.n), dtype=np.float64)
+        _check(lib().qs_batch_run(self.handle, _p(out)))
+        return out
+
+    def amplitudes(self, i: int) -> np.ndarray:
+        out = np.zeros(2 << self.n[i], dtype=np.float64)
+        _check(lib().qs_batch_state_copy_out(self.handle, i, _p(out)))
+        return out.view(np.complex128)
+
+    def close(self):
+        if self.handle:
+            lib().qs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qs_autotune(n: int, dtype: int, gl: GateList, base: qs_contract_opts | None = None) -> qs_contract_opts:
+    best = qs_contract_opts()
+    _check(lib().qs_autotune(n, dtype, gl.ptr, gl.count, ctypes.byref(base) if base is not None else None,
+                             ctypes.byref(best)))
+    return best
+
+
 def qs_profile_enable(on: bool):
     _check(lib().qs_profile_enable(1 if on else 0))
 

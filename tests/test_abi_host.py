@@ -177,3 +177,41 @@ def test_compression_on_paper_style_circuit(Q):
         assert info.max_k <= 5
     finally:
         Q.qs_plan_destroy(plan)
+
+
+def test_pass_features_on_host(Q):
+    """Pass features are host-side: a CNOT/CZ-only circuit gives only
+    monomial blocks; a dense-U3 circuit at k_max = 5 gives MFMA-width blocks."""
+    from paper_2509_04955_amd import costmodel
+
+    F = Q.lib().qs_costmodel_num_features()
+    mono = qsynth.random_circuit(20, 80, seed=3, kinds=["cx", "cz", "rz"])
+    plan, _ = _plan(Q, mono, k_max=3, tile_qubits=12)
+    try:
+        f = costmodel.pass_features(plan)
+        assert f.shape == (Q.qs_plan_info_get(plan).n_passes, F)
+        assert np.all(f[:, 10] > 0) and np.all(f[:, 5:10] == 0)   # only monomial blocks
+        assert np.allclose(f[:, 0], 20 / 32) and np.allclose(f[:, 1], 12 / 16)
+    finally:
+        Q.qs_plan_destroy(plan)
+    dense = qsynth.brickwork(20, 6, seed=1)
+    plan, _ = _plan(Q, dense, k_max=5, tile_qubits=12)
+    try:
+        f = costmodel.pass_features(plan)
+        assert np.sum(f[:, 8] + f[:, 9]) > 0   # k = 4, 5 dense blocks -> MFMA kind
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+def test_learned_strategy_without_model_falls_back_to_greedy(Q):
+    c = qsynth.random_circuit(12, 100, seed=2)
+    a, _ = _plan(Q, c, k_max=4, tile_qubits=10)
+    b, _ = _plan(Q, c, k_max=4, tile_qubits=10, strategy=Q.STRATEGY_LEARNED)
+    try:
+        ia, ib = Q.qs_plan_info_get(a), Q.qs_plan_info_get(b)
+        assert ia.n_blocks == ib.n_blocks and ia.n_passes == ib.n_passes
+        for i in range(ia.n_blocks):
+            assert Q.qs_plan_block(a, i, False)[2] == Q.qs_plan_block(b, i, False)[2]
+    finally:
+        Q.qs_plan_destroy(a)
+        Q.qs_plan_destroy(b)
