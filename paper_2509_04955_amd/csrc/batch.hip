@@ -33,7 +33,10 @@ namespace {
 using namespace tiledev;
 
 constexpr int kPassItem = 0, kEnergyItem = 1;
-constexpr uint32_t kSpinLimit = 1u << 24;
+// A dependency wait gives up after kWaitSeconds of wall-clock time (the device
+// wall clock, read with s_memrealtime): a wait that long means the item it
+// waits for will not arrive, and the kernel then drains with an error record.
+constexpr double kWaitSeconds = 1.0;
 constexpr uint64_t kPairsPerItem = 1ull << 16;
 
 struct Seg {
@@ -76,6 +79,33 @@ __device__ __forceinline__ uint32_t atomic_load_acq(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The persistent kernel below is written without lane-divergent branches:
+// control work runs on wave 0 under a condition made wave-uniform with
+// readfirstlane, lane-0-only effects are selects, and per-wave results are
+// stored by every lane of the wave (same value, same address).  This keeps the
+// compiler from restructuring the work loop around divergent regions (with a
+// `threadIdx.x == 0` region at the loop tail it produced a nested loop in which
+// lanes other than lane 0 re-entered the barrier without a new dequeue).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+// Fixed-order FP64 sum of one value per thread over the workgroup.
+__device__ double wg_sum_values(double s, double *red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    __syncthreads();
+    red[wave_id()] = s;
+    __syncthreads();
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < TT / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
 // Fixed-order FP64 sum over `count` doubles by the whole workgroup.
 __device__ double wg_sum(const double *v, uint32_t count, double *red) {
     double s = 0;
@@ -83,7 +113,7 @@ __device__ double wg_sum(const double *v, uint32_t count, double *red) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    red[wave_id()] = s;  // every lane holds the wave sum
     __syncthreads();
     double t = 0;
 #pragma unroll
@@ -135,16 +165,8 @@ __device__ void run_tile(typename AmpOf<R>::A *psi, const PassDev &pd, uint64_t 
             nacc += d.x * d.x + d.y * d.y;
         }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) nacc += __shfl_xor(nacc, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0;
-#pragma unroll
-        for (int w = 0; w < TT / 64; ++w) s += red[w];
-        *partial_out = s;
-    }
+    const double tot = wg_sum_values(nacc, red);
+    if (wave_id() == 0) *partial_out = tot;  // same value from every lane of wave 0
 }
 
 __device__ __forceinline__ uint64_t ins0(uint64_t x, int p) {
@@ -190,17 +212,24 @@ __global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int 
                                               const uint64_t *__restrict__ xs, const uint64_t *__restrict__ zs,
                                               double *__restrict__ partials, double *__restrict__ eparts,
                                               uint32_t *__restrict__ done, unsigned long long *__restrict__ queue,
-                                              uint32_t *__restrict__ error) {
+                                              uint32_t *__restrict__ error, unsigned long long *__restrict__ diag,
+                                              uint64_t wait_ticks) {
     using A = typename AmpOf<R>::A;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *tile = reinterpret_cast<A *>(smem_raw);
     __shared__ double red[TT / 64];
     __shared__ unsigned long long s_item;
     __shared__ int s_ok;
+    const bool lane0 = (threadIdx.x & 63) == 0;
+    const bool w0 = wave_id() == 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1ull);
+        // ---- dequeue (wave 0; lane 0 adds 1, the other lanes add 0) ----
+        if (w0) {
+            const unsigned long long t = atomicAdd(queue, lane0 ? 1ull : 0ull);
+            s_item = uniform64(t);
+        }
         __syncthreads();
-        const uint64_t item = s_item;
+        const uint64_t item = uniform64(s_item);
         __syncthreads();
         if (item >= total_items) break;
         int lo = 0, hi = nsegs - 1;  // last segment with first <= item
@@ -220,22 +249,40 @@ __global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int 
         } else {
             need = st.total_tiles;
         }
-        // ---- acquire: wait for the items this one depends on ----
-        if (threadIdx.x == 0) {
-            uint32_t spins = 0;
+        // ---- acquire: wave 0 waits for the items this one depends on ----
+        if (w0) {
             int ok = 1;
-            while (atomic_load_acq(done + sg.state) < need) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit || __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    atomicOr(error, 1u);
-                    ok = 0;
-                    break;
+            uint32_t seen = __builtin_amdgcn_readfirstlane(atomic_load_acq(done + sg.state));
+            if (seen < need) {
+                const uint64_t t0 = uniform64(wall_clock64());
+                for (;;) {
+                    __builtin_amdgcn_s_sleep(8);
+                    const uint32_t err = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (err) {
+                        ok = 0;
+                        break;
+                    }
+                    if (uniform64(wall_clock64()) - t0 > wait_ticks) {
+                        const uint32_t prev = __builtin_amdgcn_readfirstlane(atomicCAS(error, 0u, lane0 ? 1u : 0u));
+                        if (prev == 0u) {
+                            diag[0] = (unsigned long long)sg.state;
+                            diag[1] = need;
+                            diag[2] = seen;
+                            diag[3] = item;
+                        }
+                        ok = 0;
+                        break;
+                    }
+                    seen = __builtin_amdgcn_readfirstlane(atomic_load_acq(done + sg.state));
+                    if (seen >= need) break;
                 }
             }
             s_ok = ok;
         }
         __syncthreads();
-        if (!s_ok) break;
+        const int ok_all = __builtin_amdgcn_readfirstlane(s_ok);
+        if (!ok_all) break;
         __threadfence();
         A *psi = reinterpret_cast<A *>(st.amp);
         if (sg.kind == kPassItem) {
@@ -246,9 +293,10 @@ __global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int 
             }
             run_tile<R, WIDE>(psi, *pd, local, sc, tile, red, partials + pd->part_off + local);
             __syncthreads();
-            if (threadIdx.x == 0) {
+            // ---- release: wave 0 publishes the finished tile ----
+            if (w0) {
                 __threadfence();
-                atomicAdd(done + sg.state, 1u);
+                atomicAdd(done + sg.state, lane0 ? 1u : 0u);
             }
         } else {
             // energy item: (term group, chunk)
@@ -261,20 +309,11 @@ __global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int 
                 if (term >= st.nterms) break;
                 const uint64_t x = xs[st.term0 + term], z = zs[st.term0 + term];
                 const uint64_t u0 = (x == 0 ? 2 : 1) * chunk * cl, u1 = u0 + (x == 0 ? 2 : 1) * cl;
-                double s = pauli_partial<A>(psi, x, z, u0, u1);
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-                if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    double t = 0;
-#pragma unroll
-                    for (int w = 0; w < TT / 64; ++w) t += red[w];
-                    eparts[st.epart0 + term * st.nchunks + chunk] = t;
-                }
-                __syncthreads();
+                const double tot = wg_sum_values(pauli_partial<A>(psi, x, z, u0, u1), red);
+                if (w0) eparts[st.epart0 + term * st.nchunks + chunk] = tot;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -343,7 +382,8 @@ struct qs_batch_s {
     uint64_t *d_x = nullptr, *d_z = nullptr;
     double *d_coeff = nullptr, *d_partials = nullptr, *d_eparts = nullptr, *d_energy = nullptr;
     uint32_t *d_done = nullptr, *d_error = nullptr;
-    unsigned long long *d_queue = nullptr;
+    unsigned long long *d_queue = nullptr, *d_diag = nullptr;
+    uint64_t wait_ticks = 0;
     bool wide = false;
     size_t lds = 0;
     unsigned grid = 1;
@@ -353,7 +393,7 @@ struct qs_batch_s {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         void *bufs[] = {d_amps, d_segs, d_states, d_passes, d_x, d_z, d_coeff, d_partials, d_eparts, d_energy,
-                        d_done, d_error, d_queue};
+                        d_done, d_error, d_queue, d_diag};
         for (void *b : bufs)
             if (b) hipFree(b);
         for (qs_plan_s *p : plans) qs_plan_destroy(p);
@@ -386,7 +426,7 @@ qs_status enqueue_batch(qs_batch_s &b, hipStream_t st) {
 #define QS_BATCH(R, W)                                                                                        \
     hipLaunchKernelGGL((k_batch<R, W>), dim3(b.grid), dim3(TT), b.lds, st, b.d_segs, b.nsegs, b.total_items,   \
                        b.d_states, b.d_passes, b.d_x, b.d_z, b.d_partials, b.d_eparts, b.d_done, b.d_queue,   \
-                       b.d_error)
+                       b.d_error, b.d_diag, b.wait_ticks)
     if (b.dtype == QS_C64) {
         if (b.wide) QS_BATCH(float, true);
         else QS_BATCH(float, false);
@@ -565,7 +605,15 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
     if (e == hipSuccess) e = hipMalloc(&b->d_done, n_states * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&b->d_error, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&b->d_queue, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&b->d_diag, 4 * sizeof(unsigned long long));
     if (e != hipSuccess) return fail(hip_fail(e, "hipMalloc(batch)"));
+    {
+        int dev0 = 0, khz = 0;
+        e = hipGetDevice(&dev0);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev0);
+        if (e != hipSuccess || khz <= 0) return fail(e != hipSuccess ? hip_fail(e, "wall clock rate") : QS_EDEVICE);
+        b->wait_ticks = (uint64_t)(kWaitSeconds * 1000.0 * khz);
+    }
     // ---- persistent grid: resident workgroups only ----
     b->lds = ab << maxt;
     const void *kern = dt == QS_C64 ? (b->wide ? batch_kernel<float, true>() : batch_kernel<float, false>())
@@ -611,11 +659,15 @@ qs_status qs_batch_run(qs_batch b, double *energies) {
     QS_CHECK(b != nullptr, QS_EINVAL, "null batch");
     QS_HIP(hipGraphLaunch(b->exec, b->stream));
     uint32_t err = 0;
+    unsigned long long dg[4] = {0, 0, 0, 0};
     QS_HIP(hipMemcpyAsync(&err, b->d_error, sizeof err, hipMemcpyDeviceToHost, b->stream));
+    QS_HIP(hipMemcpyAsync(dg, b->d_diag, sizeof dg, hipMemcpyDeviceToHost, b->stream));
     if (energies)
         QS_HIP(hipMemcpyAsync(energies, b->d_energy, b->nstates * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     QS_HIP(hipStreamSynchronize(b->stream));
-    QS_CHECK(err == 0, QS_EDEVICE, "batch kernel: a dependency wait timed out");
+    QS_CHECK(err == 0, QS_EDEVICE,
+             "batch kernel: dependency wait timed out (state %llu needed %llu finished tiles, saw %llu; item %llu)",
+             dg[0], dg[1], dg[2], dg[3]);
     return QS_OK;
 }
 
