@@ -47,7 +47,168 @@ def parse():
                     help="Pauli exponentials timed gate-by-gate vs fused (0 = skip)")
     ap.add_argument("--cpu-gates", type=int, default=12,
                     help="gates of the circuit the FP64 oracle runs at full size (0 = skip)")
+    ap.add_argument("--mode", default="ucc", choices=["ucc", "copy", "batch", "learned", "brickwork"],
+                    help="ucc: the benchmark line; copy: device copy of one state-sized buffer "
+                         "(achievable streaming bandwidth and counter calibration); batch: 256 HEA states "
+                         "in one graph launch; learned: cost-model plan vs greedy at --n qubits; "
+                         "brickwork: 28-qubit brickwork, complex64 and complex128, plain vs fused")
+    ap.add_argument("--states", type=int, default=256)
     return ap.parse_args()
+
+
+def copy_mode(a):
+    """Streaming ceiling: copy S = 8 * 2^n bytes with the library's copy kernel."""
+    import torch
+
+    from paper_2509_04955_amd import qsim as Q
+
+    S = 8 << a.n
+    src = torch.ones(S // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        Q.qs_copy(dst.data_ptr(), src.data_ptr(), S, stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.steps):
+        Q.qs_copy(dst.data_ptr(), src.data_ptr(), S, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    print(json.dumps({"mode": "copy", "bytes_copied": S, "ms": round(ms, 4),
+                      "gbs": round(2 * S / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
+def _timed(fn, reps=1):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_mode(a):
+    """256 hardware-efficient-ansatz states (12..22 qubits, 8 layers RY/RZ + CZ ring),
+    a 200-term Pauli sum each, all in one hipGraph launch (autotuned plans)."""
+    import numpy as np
+
+    import qsynth
+    from paper_2509_04955_amd import qsim as Q
+
+    circuits, hams = qsynth.hea_batch(a.states, 12, 22, layers=8, n_terms=200, seed=4)
+    t0 = time.perf_counter()
+    b = Q.Batch(circuits, hams, Q.opts(k_max=0, tile_qubits=0))
+    create_s = time.perf_counter() - t0
+    E = b.run()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        E = b.run()
+    ms = (time.perf_counter() - t0) / a.steps * 1e3
+    amps = sum(1 << c.n for c in circuits)
+    out = {"mode": "batch", "states": a.states, "ms_per_batch": round(ms, 3),
+           "states_per_s": round(a.states / (ms / 1e3), 1), "amplitudes": amps,
+           "gates": sum(len(c) for c in circuits), "terms": sum(len(h) for h in hams),
+           "create_s": round(create_s, 2), "energy_mean": float(np.mean(E))}
+    # CPU baseline: the FP64 oracle on a sample of states (energy error of the GPU result)
+    import oracle
+
+    sample = list(range(0, a.states, max(1, a.states // 8)))[:8]
+    t0 = time.perf_counter()
+    errs = []
+    for i in sample:
+        psi = oracle.run(circuits[i])
+        e = oracle.expect_pauli_sum(psi, circuits[i].n, hams[i].x, hams[i].z, hams[i].coeff)
+        errs.append(abs(e - E[i]))
+    cpu_s = time.perf_counter() - t0
+    frac = sum(1 << circuits[i].n for i in sample) / amps
+    out["cpu_baseline"] = {"value": round(len(sample) / cpu_s, 3), "unit": "states/s", "cores": oracle.get_threads(),
+                           "kind": "oracle", "sample": f"{len(sample)} of {a.states} states ({frac:.3f} of the "
+                           f"amplitudes), FP64 circuit + energy, {cpu_s:.1f} s"}
+    out["max_energy_error_vs_fp64"] = float(max(errs))
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def learned_mode(a):
+    """Cost model trained on the library's own pass timings (smaller states),
+    then the learned plan vs the fixed-width greedy plan on an n-qubit random
+    U3 + CNOT circuit (depth 30), complex64."""
+    import numpy as np
+    import torch
+
+    import qsynth
+    from paper_2509_04955_amd import costmodel as CM
+    from paper_2509_04955_amd import qsim as Q
+
+    n = a.n
+    train = []
+    for nt in sorted({min(n, 26), min(n, 28)}):
+        train += [qsynth.random_u3_cnot(nt, 6, seed=31), qsynth.ucc(nt, 30, seed=32)[0],
+                  qsynth.brickwork(nt, 6, seed=33), qsynth.hea(nt, 3, seed=(34, 0))]
+    t0 = time.perf_counter()
+    X, y, us = CM.collect(train, widths=(1, 2, 3, 4, 5, 6), tiles=(12, 13), reps=3, max_passes=24)
+    collect_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = CM.train(X, y, epochs=300, batch=64, lr=3e-3, seed=1)
+    train_s = time.perf_counter() - t0
+    corr = float(np.corrcoef(CM.predict(X), y)[0, 1])
+    c = qsynth.random_u3_cnot(n, 30, seed=5)
+    gl = Q.GateList(c)
+    t0 = time.perf_counter()
+    greedy = Q.qs_contract(n, gl, Q.opts(k_max=5, tile_qubits=13))
+    tg_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    learned = Q.qs_contract(n, gl, Q.opts(k_max=5, tile_qubits=13, strategy=Q.STRATEGY_LEARNED))
+    tl_plan = time.perf_counter() - t0
+    ig, il = Q.qs_plan_info_get(greedy), Q.qs_plan_info_get(learned)
+    st = Q.State(n, Q.QS_C64)
+    ms_g = _timed(lambda: (st.set_basis(0), st.apply_plan(greedy)))
+    ms_l = _timed(lambda: (st.set_basis(0), st.apply_plan(learned)))
+    out = {"mode": "learned", "n": n, "gates": len(c), "train_rows": int(len(y)), "train_loss": loss,
+           "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
+           "greedy": {"passes": int(ig.n_passes), "blocks": int(ig.n_blocks), "ms": round(ms_g, 2),
+                      "plan_s": round(tg_plan, 2)},
+           "learned": {"passes": int(il.n_passes), "blocks": int(il.n_blocks), "ms": round(ms_l, 2),
+                       "plan_s": round(tl_plan, 2)},
+           "gain": round(ms_g / ms_l, 3)}
+    st.close()
+    Q.qs_plan_destroy(greedy)
+    Q.qs_plan_destroy(learned)
+    print(json.dumps(out), flush=True)
+
+
+def brickwork_mode(a):
+    """28-qubit brickwork (Haar U3 on every qubit + alternating CNOT pairs,
+    depth 40): complex64 and complex128, gate-by-gate vs fused (k_max 5)."""
+    import qsynth
+    from paper_2509_04955_amd import qsim as Q
+
+    n = min(a.n, 28)
+    c = qsynth.brickwork(n, 40, seed=2)
+    gl = Q.GateList(c)
+    out = {"mode": "brickwork", "n": n, "gates": len(c)}
+    for dt, name in ((Q.QS_C64, "c64"), (Q.QS_C128, "c128")):
+        st = Q.State(n, dt)
+        kmax = 5
+        plan = Q.qs_contract(n, gl, Q.opts(k_max=kmax, dtype=dt))
+        info = Q.qs_plan_info_get(plan)
+        ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
+        ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
+        S = (8 if dt == Q.QS_C64 else 16) * (1 << n)
+        out[name] = {"plain_ms": round(ms_plain, 2), "fused_ms": round(ms_fused, 2),
+                     "speedup": round(ms_plain / ms_fused, 2), "passes": int(info.n_passes),
+                     "fused_effective_gbs": round((info.n_passes * 2 + 1) * S / (ms_fused * 1e-3) / 1e9, 1)}
+        st.close()
+        Q.qs_plan_destroy(plan)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -56,6 +217,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               "(the multi-GPU path is not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if a.mode != "ucc":
+        {"copy": copy_mode, "batch": batch_mode, "learned": learned_mode, "brickwork": brickwork_mode}[a.mode](a)
+        return
     import numpy as np
     import torch
 

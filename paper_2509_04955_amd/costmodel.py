@@ -37,7 +37,7 @@ def time_passes(plan, dtype: int, reps: int = 3) -> np.ndarray:
 def collect(circuits, dtype: int = Q.QS_C64, widths=(1, 2, 3, 4, 5, 6), tiles=(12, 13), reps: int = 3,
             max_passes: int = 64):
     """Timing dataset over circuits x widths x tiles (the first `max_passes`
-    passes of each plan are timed).  Returns (X, log_us, us)."""
+    passes of each plan are timed).  Returns (X, target, us)."""
     xs, ys = [], []
     for c in circuits:
         gl = Q.GateList(c)
@@ -59,7 +59,17 @@ def collect(circuits, dtype: int = Q.QS_C64, widths=(1, 2, 3, 4, 5, 6), tiles=(1
                 ys.append(us)
     X = np.concatenate(xs).astype(np.float32)
     us = np.concatenate(ys)
-    return X, np.log(us).astype(np.float32), us
+    return X, target(us, X), us
+
+
+def target(us: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Training target: log of the pass time scaled to 2^30 amplitudes
+    (log(us) - (n - 30) ln 2, n = 32 * feature 0).  A pass streams the whole
+    state, so this removes the size dependence the model would otherwise
+    have to extrapolate; candidate passes of one plan share n, so the
+    planner's choice is unchanged by the shift."""
+    n = np.rint(X[:, 0] * 32.0)
+    return (np.log(us) - (n - 30.0) * math.log(2.0)).astype(np.float32)
 
 
 def train(X: np.ndarray, y: np.ndarray, epochs: int = 400, batch: int = 64, lr: float = 3e-3, seed: int = 1):

@@ -34,6 +34,18 @@ struct M2 {
     R ur[4], ui[4];
 };
 
+// Each sweep reads and writes every amplitude it touches once: 16-byte
+// accesses are issued non-temporal so they do not displace cache contents.
+typedef float nt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const nt4 v = __builtin_nontemporal_load(reinterpret_cast<const nt4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 v) {
+    const nt4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt4 *>(p));
+}
+
 // (x, y) = U (a, b) for complex a, b.
 template <typename R>
 __device__ __forceinline__ void apply2(const M2<R> &m, R ar, R ai, R br, R bi, R &xr, R &xi, R &yr, R &yi) {
@@ -55,7 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_1q_c64_q0(float4 *__restrict__ psi
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             uint64_t u = base_ + j * kThreads + threadIdx.x;
-            if (u < units) v[j] = psi[u];
+            if (u < units) v[j] = ld_nt(psi + u);
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
@@ -63,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_1q_c64_q0(float4 *__restrict__ psi
             if (u < units) {
                 float4 o;
                 apply2(m, v[j].x, v[j].y, v[j].z, v[j].w, o.x, o.y, o.z, o.w);
-                psi[u] = o;
+                st_nt(psi + u, o);
             }
         }
     }
@@ -81,8 +93,8 @@ __global__ __launch_bounds__(kThreads) void k_1q_c64_pair(float2 *__restrict__ p
             uint64_t u = base_ + j * kThreads + threadIdx.x;
             idx[j] = ins0(u << 1, q);
             if (u < units) {
-                a[j] = *reinterpret_cast<const float4 *>(psi + idx[j]);
-                b[j] = *reinterpret_cast<const float4 *>(psi + idx[j] + stride);
+                a[j] = ld_nt(reinterpret_cast<const float4 *>(psi + idx[j]));
+                b[j] = ld_nt(reinterpret_cast<const float4 *>(psi + idx[j] + stride));
             }
         }
 #pragma unroll
@@ -92,8 +104,8 @@ __global__ __launch_bounds__(kThreads) void k_1q_c64_pair(float2 *__restrict__ p
                 float4 x, y;
                 apply2(m, a[j].x, a[j].y, b[j].x, b[j].y, x.x, x.y, y.x, y.y);
                 apply2(m, a[j].z, a[j].w, b[j].z, b[j].w, x.z, x.w, y.z, y.w);
-                *reinterpret_cast<float4 *>(psi + idx[j]) = x;
-                *reinterpret_cast<float4 *>(psi + idx[j] + stride) = y;
+                st_nt(reinterpret_cast<float4 *>(psi + idx[j]), x);
+                st_nt(reinterpret_cast<float4 *>(psi + idx[j] + stride), y);
             }
         }
     }
@@ -110,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_1q_c64_shfl(float4 *__restrict__ p
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             uint64_t u = base_ + j * kThreads + threadIdx.x;
-            if (u < units) v[j] = psi[u];
+            if (u < units) v[j] = ld_nt(psi + u);
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
@@ -131,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_1q_c64_shfl(float4 *__restrict__ p
                     apply2(m, p.x, p.y, v[j].x, v[j].y, dr, di, o.x, o.y);
                     apply2(m, p.z, p.w, v[j].z, v[j].w, dr, di, o.z, o.w);
                 }
-                psi[u] = o;
+                st_nt(psi + u, o);
             }
         }
     }
@@ -180,8 +192,8 @@ __global__ __launch_bounds__(kThreads) void k_ctrl_c64_vec(float2 *__restrict__ 
             uint64_t u = base_ + j * kThreads + threadIdx.x;
             idx[j] = ins0(ins0(u << 1, lo), hi) | cm;
             if (u < units) {
-                a[j] = *reinterpret_cast<const float4 *>(psi + idx[j]);
-                b[j] = *reinterpret_cast<const float4 *>(psi + idx[j] + stride);
+                a[j] = ld_nt(reinterpret_cast<const float4 *>(psi + idx[j]));
+                b[j] = ld_nt(reinterpret_cast<const float4 *>(psi + idx[j] + stride));
             }
         }
 #pragma unroll
@@ -191,8 +203,8 @@ __global__ __launch_bounds__(kThreads) void k_ctrl_c64_vec(float2 *__restrict__ 
                 float4 x, y;
                 apply2(m, a[j].x, a[j].y, b[j].x, b[j].y, x.x, x.y, y.x, y.y);
                 apply2(m, a[j].z, a[j].w, b[j].z, b[j].w, x.z, x.w, y.z, y.w);
-                *reinterpret_cast<float4 *>(psi + idx[j]) = x;
-                *reinterpret_cast<float4 *>(psi + idx[j] + stride) = y;
+                st_nt(reinterpret_cast<float4 *>(psi + idx[j]), x);
+                st_nt(reinterpret_cast<float4 *>(psi + idx[j] + stride), y);
             }
         }
     }
@@ -411,19 +423,23 @@ __global__ __launch_bounds__(kThreads) void k_fill_basis(uint4 *__restrict__ w, 
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+template <bool NT>
+__global__ __launch_bounds__(kThreads) void k_copy(float4 *__restrict__ dst, const float4 *__restrict__ src,
                                                    uint64_t words) {
     UNIT_LOOP(words) {
-        uint4 v[kUnroll];
+        float4 v[kUnroll];
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             uint64_t u = base_ + j * kThreads + threadIdx.x;
-            if (u < words) v[j] = src[u];
+            if (u < words) v[j] = NT ? ld_nt(src + u) : src[u];
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             uint64_t u = base_ + j * kThreads + threadIdx.x;
-            if (u < words) dst[u] = v[j];
+            if (u < words) {
+                if (NT) st_nt(dst + u, v[j]);
+                else dst[u] = v[j];
+            }
         }
     }
 }
@@ -695,7 +711,17 @@ qs_status launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st
     QS_CHECK(bytes % 16 == 0, QS_EINVAL, "copy size must be a multiple of 16 bytes");
     const uint64_t words = bytes / 16;
     prof_begin(st, QS_PROF_COPY, 2.0 * bytes, 0);
-    hipLaunchKernelGGL(k_copy, grid_for(words), dim3(kThreads), 0, st, (uint4 *)dst, (const uint4 *)src, words);
+    static int nt = -1;
+    if (nt < 0) {
+        const char *e = getenv("QS_COPY_TEMPORAL");
+        nt = (e && atoi(e) != 0) ? 0 : 1;
+    }
+    if (nt)
+        hipLaunchKernelGGL(k_copy<true>, grid_for(words), dim3(kThreads), 0, st, (float4 *)dst, (const float4 *)src,
+                           words);
+    else
+        hipLaunchKernelGGL(k_copy<false>, grid_for(words), dim3(kThreads), 0, st, (float4 *)dst, (const float4 *)src,
+                           words);
     prof_end(st);
     QS_HIP(hipGetLastError());
     return QS_OK;

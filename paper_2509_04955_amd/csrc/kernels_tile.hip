@@ -38,12 +38,28 @@ using namespace tiledev;
 
 // Amplitude vectors each lane prefetches for the next tile while the current
 // tile is being processed (16-byte vectors: 2 complex64 or 1 complex128).
-constexpr int kPrefetch = 8;
+constexpr int kPrefetch = 6;
 
+// Streaming accesses to the state bypass cache retention (non-temporal): each
+// amplitude is read once and written once per pass.
+typedef float nt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const nt4 v = __builtin_nontemporal_load(reinterpret_cast<const nt4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 v) {
+    const nt4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt4 *>(p));
+}
+
+// Tile index li of 16-byte vector vi = tid + TT*j splits into a per-thread
+// part (tid*APV, below TT*APV) and a per-j part (j*TT*APV); both the global
+// offset map and the LDS swizzle are bitwise, so each address is the per-thread
+// constant combined with a wave-uniform per-j value.
 template <typename R, bool WIDE>
-__global__ __launch_bounds__(TT, (sizeof(R) == 4 && !WIDE) ? 2 : 1) void k_tile_pass(typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa,
-                                                  const BlockDev *__restrict__ blocks, const R *__restrict__ pool,
-                                                  const double *__restrict__ scale_in, double *__restrict__ partials) {
+__global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_tile_pass(
+    typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
+    const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials) {
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
@@ -52,58 +68,54 @@ __global__ __launch_bounds__(TT, (sizeof(R) == 4 && !WIDE) ? 2 : 1) void k_tile_
     __shared__ double red[TT / 64];
     const int T = pa.t;
     const uint32_t tsize = 1u << T;
-    const uint32_t nvec = tsize / APV;                  // 16-byte vectors per tile
     const R sc = pa.apply_scale ? (R)(*scale_in) : (R)1;
+    const uint32_t my_li = threadIdx.x * APV;
+    const bool active = my_li < tsize;             // small tiles: fewer vectors than threads
+    const uint64_t g_t = active ? tile_offset(my_li, pa) : 0;
+    const uint32_t s_t = sw(my_li);
+    const uint32_t nj = (tsize + TT * APV - 1) / (TT * APV);   // vectors per thread
     float4 pre[kPrefetch];
-
-    auto gload = [&](uint64_t base, uint32_t vi) -> float4 {
-        const uint32_t li = vi * APV;
-        return *reinterpret_cast<const float4 *>(psi + (base | tile_offset(li, pa)));
+    auto gaddr = [&](uint64_t base, uint32_t j) -> const float4 * {
+        return reinterpret_cast<const float4 *>(psi + (base | g_t | tile_offset(j * TT * APV, pa)));
     };
-    auto lds_put = [&](uint32_t vi, float4 v) {
-        const uint32_t li = vi * APV;
+    auto lds_put = [&](uint32_t j, float4 v) {
+        const uint32_t si = s_t ^ sw(j * TT * APV);
         if constexpr (F32) {
             v.x *= sc;
             v.y *= sc;
             v.z *= sc;
             v.w *= sc;
-            *reinterpret_cast<float4 *>(tile + sw(li)) = v;
+            *reinterpret_cast<float4 *>(tile + si) = v;
         } else {
             double2 d = *reinterpret_cast<double2 *>(&v);
             d.x *= sc;
             d.y *= sc;
-            tile[sw(li)] = d;
+            tile[si] = d;
         }
     };
-    // prologue: prefetch the first tile
     uint64_t tileid = blockIdx.x;
-    if (tileid < ntiles) {
+    if (tileid < ntiles && active) {
         const uint64_t base = tile_base(tileid, pa);
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
-            const uint32_t vi = threadIdx.x + j * TT;
-            if (vi < nvec) pre[j] = gload(base, vi);
-        }
+        for (int j = 0; j < kPrefetch; ++j)
+            if ((uint32_t)j < nj) pre[j] = ld_nt(gaddr(base, j));
     }
     for (; tileid < ntiles; tileid += gridDim.x) {
         const uint64_t base = tile_base(tileid, pa);
-        // ---- prefetched part into LDS, the rest loaded directly ----
+        if (active) {
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
-            const uint32_t vi = threadIdx.x + j * TT;
-            if (vi < nvec) lds_put(vi, pre[j]);
+            for (int j = 0; j < kPrefetch; ++j)
+                if ((uint32_t)j < nj) lds_put(j, pre[j]);
+            for (uint32_t j = kPrefetch; j < nj; ++j) lds_put(j, ld_nt(gaddr(base, j)));
         }
-        for (uint32_t vi = threadIdx.x + kPrefetch * TT; vi < nvec; vi += TT) lds_put(vi, gload(base, vi));
         __syncthreads();
         // ---- start fetching the next tile ----
         const uint64_t nxt = tileid + gridDim.x;
-        if (nxt < ntiles) {
+        if (nxt < ntiles && active) {
             const uint64_t nbase = tile_base(nxt, pa);
 #pragma unroll
-            for (int j = 0; j < kPrefetch; ++j) {
-                const uint32_t vi = threadIdx.x + j * TT;
-                if (vi < nvec) pre[j] = gload(nbase, vi);
-            }
+            for (int j = 0; j < kPrefetch; ++j)
+                if ((uint32_t)j < nj) pre[j] = ld_nt(gaddr(nbase, j));
         }
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
@@ -112,21 +124,22 @@ __global__ __launch_bounds__(TT, (sizeof(R) == 4 && !WIDE) ? 2 : 1) void k_tile_
         }
         // ---- store + FP64 norm partial ----
         double nacc = 0.0;
-        for (uint32_t vi = threadIdx.x; vi < nvec; vi += TT) {
-            const uint32_t li = vi * APV;
-            const float4 v = *reinterpret_cast<const float4 *>(tile + sw(li));
-            *reinterpret_cast<float4 *>(psi + (base | tile_offset(li, pa))) = v;
-            if constexpr (F32) {
-                nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
-            } else {
-                const double2 d = *reinterpret_cast<const double2 *>(&v);
-                nacc += d.x * d.x + d.y * d.y;
+        if (active) {
+            for (uint32_t j = 0; j < nj; ++j) {
+                const float4 v = *reinterpret_cast<const float4 *>(tile + (s_t ^ sw(j * TT * APV)));
+                st_nt(const_cast<float4 *>(gaddr(base, j)), v);
+                if constexpr (F32) {
+                    nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+                } else {
+                    const double2 d = *reinterpret_cast<const double2 *>(&v);
+                    nacc += d.x * d.x + d.y * d.y;
+                }
             }
         }
         if (pa.want_norm) {
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) nacc += __shfl_xor(nacc, o);
-            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
+            red[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)] = nacc;   // every lane holds the wave sum
             __syncthreads();
             if (threadIdx.x == 0) {
                 double s = 0;
@@ -257,8 +270,8 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<
             pool.push_back((R)u.real());
             pool.push_back((R)u.imag());
             pool.push_back((R)sw(o));
+            pool.push_back((R)0);
         }
-        if (d.k > 4) wide = true;
     } else if (kind == BK_MFMA) {
         (void)f32;
         d.kind = BK_MFMA;

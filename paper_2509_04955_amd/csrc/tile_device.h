@@ -166,80 +166,90 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
 
 // ---- monomial block: one nonzero per column ---------------------------------
 // y[dest(c)] = u_c x[c].  Diagonal blocks are the case dest(c) = c.  Pool entry
-// c holds (Re u_c, Im u_c, tile offset of dest(c)) so every lane reads the same
-// three values (scalar loads) and each group costs one complex multiply per
-// amplitude.  A lane reads its whole group before writing any of it.
+// c is a 4-value record (Re u_c, Im u_c, swizzled tile offset of dest(c), 0),
+// read as wave-uniform scalars when a group fits one lane.  A group of 2^K amplitudes is handled by LPG lanes of
+// one wave (LPG = 1 for K <= 3, 2^(K-3) above), each holding 8 or fewer
+// sources; the lanes of a wave issue all their LDS reads before any write, so
+// the in-place permutation is safe.
 template <int K, typename R>
-__device__ __forceinline__ void mono_group(typename AmpOf<R>::A *tile, uint32_t sb, const int *pos,
+__device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                            const R *__restrict__ E) {
     using A = typename AmpOf<R>::A;
-    constexpr int D = 1 << K;
-    A v[D];
+    constexpr int LPG = K <= 3 ? 1 : (1 << (K > 3 ? K - 3 : 0));
+    constexpr int SPL = (1 << K) / LPG;
+    constexpr int KL = K <= 3 ? K : 3;   // bits of c that index within a lane
+    int pos[K];
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    auto deposit = [&](uint32_t c) {
         uint32_t o = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if ((c >> j) & 1) o |= 1u << pos[j];
-        v[c] = tile[sb ^ sw(o)];
-    }
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        const R ur = E[3 * c], ui = E[3 * c + 1];
-        const uint32_t dst = (uint32_t)E[3 * c + 2];  // already swizzled on the host
-        A y;
-        y.x = ur * v[c].x - ui * v[c].y;
-        y.y = ur * v[c].y + ui * v[c].x;
-        tile[sb ^ dst] = y;
-    }
-}
-
-template <int K, typename R>
-__device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                           const R *__restrict__ E) {
-    int pos[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+        return o;
+    };
     const uint32_t G = 1u << (T - K);
-    auto base_of = [&](uint32_t g) {
+    const uint32_t tasks = G * LPG;
+    auto group = [&](uint32_t tk) {
+        const uint32_t g = tk / LPG, p = tk % LPG;
         uint32_t b = g;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-        return sw(b);
+        const uint32_t sb = sw(b) ^ sw(deposit(p << KL));
+        A v[SPL];
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) v[i] = tile[sb ^ sw(deposit((uint32_t)i))];
+        const uint32_t sbase = sw(b);
+        // entry c = p * SPL + i: wave-uniform (scalar loads) when LPG == 1
+        const R *Ep = E + 4 * (p * SPL);
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+            const R ur = Ep[4 * i], ui = Ep[4 * i + 1];
+            const uint32_t dst = (uint32_t)Ep[4 * i + 2];
+            A y;
+            y.x = ur * v[i].x - ui * v[i].y;
+            y.y = ur * v[i].y + ui * v[i].x;
+            tile[sbase ^ dst] = y;
+        }
     };
     if constexpr (K <= 3) {
-        if (G >= 2 * TT) {
-            for (uint32_t g = threadIdx.x; g < G; g += 2 * TT) {
-                mono_group<K, R>(tile, base_of(g), pos, E);
-                mono_group<K, R>(tile, base_of(g + TT), pos, E);
+        if (tasks >= 2 * TT) {
+            for (uint32_t tk = threadIdx.x; tk < tasks; tk += 2 * TT) {
+                group(tk);
+                group(tk + TT);
             }
             return;
         }
     }
-    for (uint32_t g = threadIdx.x; g < G; g += TT) mono_group<K, R>(tile, base_of(g), pos, E);
+    for (uint32_t tk = threadIdx.x; tk < tasks; tk += TT) group(tk);
 }
 
 // ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
-// Lane l of a wave: g = l / 16 selects the K-slice of each 16x16x4 step and the
-// output row quad, j = l % 16 the tile column.  Step s feeds B row (s/2)*4 + g
-// (real part for even s, imaginary for odd s); outputs land as complete
-// complex numbers Y[16h + 4g + q] (Re in M-tile h, Im in M-tile MT/2 + h).
+// Y = A X with A = [[Ur, -Ui], [Ui, Ur]] (2D x 2D, D = 2^K) and X the 2D x N
+// real view of the tile (rows: Re then Im of the block's 2^K amplitudes;
+// columns: the other tile positions).  v_mfma_f32_16x16x4f32: lane l supplies
+// A[l%16][kk] and B[kk][l%16] with kk = 4s + l/16 for step s; K-order is
+// chosen so step s reads row 4(s/2) + l/16 of X, real part for even s and
+// imaginary for odd s, and output register q of lane l is row 4(l/16) + q.
+// Each wave owns one 16-row M-tile (its slice of A stays in 2^(K-1) VGPRs):
+// K = 5 has 4 M-tiles, one per wave; K = 4 has 2, and the waves sharing one
+// split the columns.  Columns go in rounds of 4 chunks of 16 per wave: all
+// waves read their inputs, a barrier, then all write (in place).
 template <int K>
 __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *bd, const float *__restrict__ Asw) {
     constexpr int D = 1 << K;
     constexpr int MT = 2 * D / 16;
     constexpr int S = 2 * D / 4;
     constexpr int NB = D / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int CPW = 4 / MT;   // waves per M-tile
+    constexpr int CR = 4;         // chunks per wave per round
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gq = lane >> 4, jc = lane & 15;
+    const int mt = wave % MT, wsub = wave / MT;
     int pos[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
-    float a[MT][S];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int s = 0; s < S; ++s) a[mt][s] = Asw[(mt * S + s) * 64 + lane];
     auto deposit = [&](int r) {
         uint32_t o = 0;
 #pragma unroll
@@ -247,43 +257,64 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
             if ((r >> j) & 1) o |= 1u << pos[j];
         return o;
     };
+    float a[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) a[s] = Asw[(mt * S + s) * 64 + lane];
     uint32_t offB[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq));
-    uint32_t offC[MT / 2][4];
+    const int half = MT / 2;
+    const int part = mt >= half ? 1 : 0;  // 0: real rows, 1: imaginary rows
+    uint32_t offC[4];
 #pragma unroll
-    for (int h = 0; h < MT / 2; ++h)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) offC[h][q] = sw(deposit(16 * h + 4 * gq + q));
+    for (int q = 0; q < 4; ++q) offC[q] = sw(deposit(16 * (mt % half) + 4 * gq + q));
+    float *tf = reinterpret_cast<float *>(tile);
     const uint32_t nchunks = (1u << (T - K)) / 16;
-    for (uint32_t ch = wave; ch < nchunks; ch += TT / 64) {
-        uint32_t cb = ch * 16 + jc;
+    for (uint32_t r0 = 0; r0 < nchunks; r0 += CR * CPW) {
+        floatx4 acc[CR];
+        uint32_t cbs[CR];
+        // chunks in pairs: two independent accumulator chains per step
 #pragma unroll
-        for (int j = 0; j < K; ++j) cb = ins0_32(cb, pos[j]);
-        cb = sw(cb);
-        float2 bv[NB];
+        for (int i0 = 0; i0 < CR; i0 += 2) {
+            float2 bv[2][NB];
 #pragma unroll
-        for (int m = 0; m < NB; ++m) bv[m] = tile[cb ^ offB[m]];
-        floatx4 acc[MT];
+            for (int h = 0; h < 2; ++h) {
+                const int i = i0 + h;
+                acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+                cbs[i] = 0;
+                const uint32_t ch = r0 + wsub + CPW * i;
+                uint32_t cb = (ch < nchunks ? ch : 0) * 16 + jc;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int j = 0; j < K; ++j) cb = ins0_32(cb, pos[j]);
+                cb = sw(cb);
+                cbs[i] = cb;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float b = (s & 1) ? bv[s >> 1].y : bv[s >> 1].x;
+                for (int m = 0; m < NB; ++m) bv[h][m] = tile[cb ^ offB[m]];
+            }
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][s], b, acc[mt], 0, 0, 0);
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    acc[i0 + h] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        a[s], (s & 1) ? bv[h][s >> 1].y : bv[h][s >> 1].x, acc[i0 + h], 0, 0, 0);
         }
+        __syncthreads();
 #pragma unroll
-        for (int h = 0; h < MT / 2; ++h)
+        for (int i = 0; i < CR; ++i) {
+            const uint32_t ch = r0 + wsub + CPW * i;
+            if (ch < nchunks) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) tile[cb ^ offC[h][q]] = make_float2(acc[h][q], acc[MT / 2 + h][q]);
+                for (int q = 0; q < 4; ++q) tf[2 * (cbs[i] ^ offC[q]) + part] = acc[i][q];
+            }
+        }
+        __syncthreads();
     }
 }
 
 // ---- the pass kernel ------------------------------------------------------
-// WIDE = false keeps register use low (dense VALU blocks up to k = 3; complex64
-// k = 4, 5 through MFMA; monomial blocks up to k = 4); WIDE = true adds the
-// widest blocks.  The host picks the variant per pass.
+// WIDE = false keeps register use low (dense VALU blocks up to k = 3, complex64
+// dense k = 4, 5 through MFMA, monomial blocks of any width); WIDE = true adds
+// dense VALU blocks with k >= 4.  The host picks the variant per pass.
 template <typename R, bool WIDE>
 __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                             const R *__restrict__ pool) {
@@ -304,15 +335,9 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
         case 2: mono_block<2, R>(tile, T, bd, U); return;
         case 3: mono_block<3, R>(tile, T, bd, U); return;
         case 4: mono_block<4, R>(tile, T, bd, U); return;
-        default: break;
+        case 5: mono_block<5, R>(tile, T, bd, U); return;
+        default: mono_block<6, R>(tile, T, bd, U); return;
         }
-        if constexpr (WIDE) {
-            if (k == 5) { mono_block<5, R>(tile, T, bd, U); return; }
-        }
-        if constexpr (F32 && WIDE) {
-            if (k == 6) { mono_block<6, R>(tile, T, bd, U); return; }
-        }
-        return;
     }
     switch (k) {
     case 1: valu_block<1, R>(tile, T, bd, U); return;
