@@ -40,8 +40,8 @@ def parse():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--n-exp", type=int, default=2000)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--k-max", type=int, default=5)
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--k-max", type=int, default=0, help="0 = autotune (with --tile)")
+    ap.add_argument("--tile", type=int, default=0, help="0 = autotune (with --k-max)")
     ap.add_argument("--strategy", type=int, default=1)
     ap.add_argument("--plain-prefix", type=int, default=40,
                     help="Pauli exponentials timed gate-by-gate vs fused (0 = skip)")
@@ -231,6 +231,13 @@ def main():
     n = a.n
     circ, rots = qsynth.ucc(n, n_exp=a.n_exp, seed=a.seed)
     gl = Q.GateList(circ)
+    tune_s = 0.0
+    if a.k_max == 0 or a.tile == 0:
+        # autotuner: times candidate (k_max, t) plans on the circuit's first gates
+        t0 = time.perf_counter()
+        best = Q.qs_autotune(n, Q.QS_C64, gl, Q.opts(strategy=a.strategy, renorm=1))
+        tune_s = time.perf_counter() - t0
+        a.k_max, a.tile = best.k_max, best.tile_qubits
     t0 = time.perf_counter()
     plan = Q.qs_contract(n, gl, Q.opts(k_max=a.k_max, tile_qubits=a.tile, strategy=a.strategy, renorm=1))
     plan_s = time.perf_counter() - t0
@@ -291,10 +298,12 @@ def main():
         "data": "synthetic (seeded UCC-style Pauli-exponential circuit)",
         "config": {"workload": f"ucc n={n} n_exp={a.n_exp} seed={a.seed} complex64", "n_qubits": n,
                    "n_gates": int(info.n_gates), "n_blocks": int(info.n_blocks), "n_passes": int(info.n_passes),
-                   "k_max": a.k_max, "strategy": a.strategy, "flops_per_amp": info.flops_per_amp},
+                   "k_max": a.k_max, "tile_qubits": a.tile, "strategy": a.strategy,
+                   "flops_per_amp_dense_equiv": round(info.flops_per_amp / max(1, info.n_passes), 1)},
         "circuit_time_s": round(ms_step / 1e3, 4),
         "gates_per_s": round(info.n_gates / (ms_step / 1e3), 1),
         "plan_time_s": round(plan_s, 3),
+        "autotune_s": round(tune_s, 2),
         "norm_after": nrm,
         "roofline": roof,
     }
