@@ -56,13 +56,23 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v) {
 // part (tid*APV, below TT*APV) and a per-j part (j*TT*APV); both the global
 // offset map and the LDS swizzle are bitwise, so each address is the per-thread
 // constant combined with a wave-uniform per-j value.
-template <typename R, bool WIDE>
+//
+// NJ > 0 fixes the number of 16-byte vectors per thread at compile time (the
+// tile is exactly NJ*TT*APV amplitudes): every load and store is then
+// unconditional and the next tile's vectors beyond the prefetch depth are
+// loaded into registers after the blocks, before the stores.
+// NJ = 0 handles any tile size; vectors beyond the prefetch depth are then
+// loaded in batches whose loads are all issued before the first of them is
+// waited on.
+template <typename R, bool WIDE, int NJ>
 __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_tile_pass(
     typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
     const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials) {
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
+    constexpr int PF = NJ > 0 && NJ < kPrefetch ? NJ : kPrefetch;
+    constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *tile = reinterpret_cast<A *>(smem_raw);
     __shared__ double red[TT / 64];
@@ -70,11 +80,11 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
     const uint32_t tsize = 1u << T;
     const R sc = pa.apply_scale ? (R)(*scale_in) : (R)1;
     const uint32_t my_li = threadIdx.x * APV;
-    const bool active = my_li < tsize;             // small tiles: fewer vectors than threads
+    const bool active = NJ > 0 || my_li < tsize;   // small tiles: fewer vectors than threads
     const uint64_t g_t = active ? tile_offset(my_li, pa) : 0;
     const uint32_t s_t = sw(my_li);
-    const uint32_t nj = (tsize + TT * APV - 1) / (TT * APV);   // vectors per thread
-    float4 pre[kPrefetch];
+    const uint32_t nj = NJ > 0 ? (uint32_t)NJ : (tsize + TT * APV - 1) / (TT * APV);   // vectors per thread
+    float4 pre[PF];
     auto gaddr = [&](uint64_t base, uint32_t j) -> const float4 * {
         return reinterpret_cast<const float4 *>(psi + (base | g_t | tile_offset(j * TT * APV, pa)));
     };
@@ -93,34 +103,64 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
             tile[si] = d;
         }
     };
-    uint64_t tileid = blockIdx.x;
-    if (tileid < ntiles && active) {
-        const uint64_t base = tile_base(tileid, pa);
+    // Vectors of a generic tile beyond the prefetch depth: loaded in batches
+    // through the prefetch registers once those are in LDS.
+    auto load_rest = [&](uint64_t base) {
+        for (uint32_t j0 = PF; j0 < nj; j0 += PF) {
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j)
+            for (int i = 0; i < PF; ++i)
+                if (j0 + i < nj) pre[i] = ld_nt(gaddr(base, j0 + i));
+#pragma unroll
+            for (int i = 0; i < PF; ++i)
+                if (j0 + i < nj) lds_put(j0 + i, pre[i]);
+        }
+    };
+    uint64_t tileid = blockIdx.x;
+    if (tileid >= ntiles) return;   // whole workgroup
+    uint64_t base = tile_base(tileid, pa);
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
             if ((uint32_t)j < nj) pre[j] = ld_nt(gaddr(base, j));
+        if constexpr (EX > 0) {
+            float4 ex[EX];
+#pragma unroll
+            for (int i = 0; i < EX; ++i) ex[i] = ld_nt(gaddr(base, PF + i));
+#pragma unroll
+            for (int j = 0; j < PF; ++j) lds_put(j, pre[j]);
+#pragma unroll
+            for (int i = 0; i < EX; ++i) lds_put(PF + i, ex[i]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+                if ((uint32_t)j < nj) lds_put(j, pre[j]);
+            if constexpr (NJ == 0) load_rest(base);
+        }
     }
-    for (; tileid < ntiles; tileid += gridDim.x) {
-        const uint64_t base = tile_base(tileid, pa);
+    // Loop invariant: the tile `tileid` is in LDS (after the barrier).  The
+    // next tile's loads are issued before this tile's stores (prefetch
+    // registers before the blocks, the remaining vectors after them), so the
+    // waits for them at the bottom of the loop leave the stores in flight.
+    // On the last tile the loads re-read the current tile (in bounds, unused).
+    for (;;) {
+        __syncthreads();
+        const uint64_t nxt = tileid + gridDim.x;
+        const bool more = nxt < ntiles;   // uniform over the workgroup
+        const uint64_t nbase = more ? tile_base(nxt, pa) : base;
         if (active) {
 #pragma unroll
-            for (int j = 0; j < kPrefetch; ++j)
-                if ((uint32_t)j < nj) lds_put(j, pre[j]);
-            for (uint32_t j = kPrefetch; j < nj; ++j) lds_put(j, ld_nt(gaddr(base, j)));
-        }
-        __syncthreads();
-        // ---- start fetching the next tile ----
-        const uint64_t nxt = tileid + gridDim.x;
-        if (nxt < ntiles && active) {
-            const uint64_t nbase = tile_base(nxt, pa);
-#pragma unroll
-            for (int j = 0; j < kPrefetch; ++j)
+            for (int j = 0; j < PF; ++j)
                 if ((uint32_t)j < nj) pre[j] = ld_nt(gaddr(nbase, j));
         }
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
             apply_block<R, WIDE>(tile, T, blocks + pa.block0 + b, pool);
             __syncthreads();
+        }
+        float4 ex[EX > 0 ? EX : 1];
+        if constexpr (EX > 0) {
+#pragma unroll
+            for (int i = 0; i < EX; ++i) ex[i] = ld_nt(gaddr(nbase, PF + i));
         }
         // ---- store + FP64 norm partial ----
         double nacc = 0.0;
@@ -148,7 +188,21 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
                 partials[tileid] = s;
             }
         }
-        __syncthreads();  // the tile buffer is reused by the next tile
+        __syncthreads();  // every read of this tile from LDS is done
+        if (!more) break;
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+                if ((uint32_t)j < nj) lds_put(j, pre[j]);
+            if constexpr (EX > 0) {
+#pragma unroll
+                for (int i = 0; i < EX; ++i) lds_put(PF + i, ex[i]);
+            } else if constexpr (NJ == 0) {
+                load_rest(nbase);
+            }
+        }
+        tileid = nxt;
+        base = nbase;
     }
 }
 
@@ -189,14 +243,42 @@ __global__ __launch_bounds__(256) void k_norm_parts(const A *__restrict__ psi, u
     if (threadIdx.x == 0) parts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-template <typename R, bool WIDE>
-void set_lds_limit(size_t bytes) {
-    static size_t done = 0;
-    if (bytes > done) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile_pass<R, WIDE>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        done = bytes;
+template <typename R>
+using TileKernel = void (*)(typename AmpOf<R>::A *, uint64_t, PassArgs, const BlockDev *, const R *, const double *,
+                            double *);
+
+// Kernel variant for a pass: register footprint (wide) and, for the common
+// tile sizes of the narrow variant, the compile-time vector count.
+template <typename R>
+TileKernel<R> pick_tile_kernel(bool wide, int t) {
+    constexpr int APV = sizeof(R) == 4 ? 2 : 1;
+    const int vpt = (1 << t) / (TT * APV);   // 16-byte vectors per thread
+    if (wide) return k_tile_pass<R, true, 0>;
+    if ((1 << t) == vpt * TT * APV) {
+        if constexpr (sizeof(R) == 4) {
+            if (vpt == 4) return k_tile_pass<R, false, 4>;
+            if (vpt == 8) return k_tile_pass<R, false, 8>;
+        } else {
+            if (vpt == 8) return k_tile_pass<R, false, 8>;
+            if (vpt == 16) return k_tile_pass<R, false, 16>;
+        }
     }
+    return k_tile_pass<R, false, 0>;
+}
+
+// Raise a kernel's dynamic LDS limit once per (kernel, size).
+void set_lds_limit(const void *fn, size_t bytes) {
+    static std::vector<std::pair<const void *, size_t>> done;
+    for (auto &d : done)
+        if (d.first == fn) {
+            if (bytes > d.second) {
+                (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                d.second = bytes;
+            }
+            return;
+        }
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done.emplace_back(fn, bytes);
 }
 
 bool mfma_enabled() {
@@ -291,8 +373,8 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<
     while (pool.size() % 4) pool.push_back((R)0);  // 16-byte aligned entries
 }
 
-// Workgroups of the tile kernel resident at once on the current device.
-uint64_t resident_groups(qs_dtype dt, bool wide, size_t lds) {
+// Workgroups of a tile kernel resident at once on the current device.
+uint64_t resident_groups(const void *fn, size_t lds) {
     static int cus = 0;
     if (!cus) {
         int dev = 0;
@@ -302,14 +384,8 @@ uint64_t resident_groups(qs_dtype dt, bool wide, size_t lds) {
         if (cus <= 0) cus = 256;
     }
     int per_cu = 0;
-    hipError_t e;
-    if (dt == QS_C64) {
-        if (wide) { set_lds_limit<float, true>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<float, true>, TT, lds); }
-        else { set_lds_limit<float, false>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<float, false>, TT, lds); }
-    } else {
-        if (wide) { set_lds_limit<double, true>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<double, true>, TT, lds); }
-        else { set_lds_limit<double, false>(lds); e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pass<double, false>, TT, lds); }
-    }
+    set_lds_limit(fn, lds);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TT, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return (uint64_t)per_cu * (uint64_t)cus;
 }
@@ -397,7 +473,9 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     const bool wide = p.pass_wide[di][pass_index] != 0;
     const size_t amp = s.dtype == QS_C64 ? 8 : 16;
     const size_t lds = amp << ps.t;
-    const uint64_t resident = resident_groups(s.dtype, wide, lds);
+    const void *fn = s.dtype == QS_C64 ? reinterpret_cast<const void *>(pick_tile_kernel<float>(wide, ps.t))
+                                       : reinterpret_cast<const void *>(pick_tile_kernel<double>(wide, ps.t));
+    const uint64_t resident = resident_groups(fn, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
     const double S = std::ldexp((double)amp, s.n);
     double flops = 0;
@@ -405,20 +483,12 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
         flops += (p.h_blocks[di][b].kind == BK_MONO ? 6.0 : 8.0 * std::ldexp(1.0, p.h_blocks[di][b].k)) *
                  std::ldexp(1.0, s.n);
     prof_begin(s.stream, QS_PROF_TILE, 2 * S, flops);
-#define QS_LAUNCH_TILE(R, A, W)                                                                                   \
-    do {                                                                                                          \
-        set_lds_limit<R, W>(lds);                                                                                 \
-        hipLaunchKernelGGL((k_tile_pass<R, W>), grid, dim3(TT), lds, s.stream, (A *)s.amp, ntiles, pa,            \
-                           p.d_blocks[di], (const R *)p.d_pool[di], s.d_slots + 1, s.d_partials);                 \
-    } while (0)
-    if (s.dtype == QS_C64) {
-        if (wide) QS_LAUNCH_TILE(float, float2, true);
-        else QS_LAUNCH_TILE(float, float2, false);
-    } else {
-        if (wide) QS_LAUNCH_TILE(double, double2, true);
-        else QS_LAUNCH_TILE(double, double2, false);
-    }
-#undef QS_LAUNCH_TILE
+    if (s.dtype == QS_C64)
+        hipLaunchKernelGGL(pick_tile_kernel<float>(wide, ps.t), grid, dim3(TT), lds, s.stream, (float2 *)s.amp, ntiles,
+                           pa, p.d_blocks[di], (const float *)p.d_pool[di], s.d_slots + 1, s.d_partials);
+    else
+        hipLaunchKernelGGL(pick_tile_kernel<double>(wide, ps.t), grid, dim3(TT), lds, s.stream, (double2 *)s.amp,
+                           ntiles, pa, p.d_blocks[di], (const double *)p.d_pool[di], s.d_slots + 1, s.d_partials);
     prof_end(s.stream);
     QS_HIP(hipGetLastError());
     return QS_OK;
