@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--k-max", type=int, default=0, help="0 = autotune (with --tile)")
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune (with --k-max)")
+    ap.add_argument("--low", type=int, default=0, help="fixed low qubits per tile; 0 = autotuned / library default")
     ap.add_argument("--strategy", type=int, default=1)
     ap.add_argument("--plain-prefix", type=int, default=40,
                     help="Pauli exponentials timed gate-by-gate vs fused (0 = skip)")
@@ -233,13 +234,14 @@ def main():
     gl = Q.GateList(circ)
     tune_s = 0.0
     if a.k_max == 0 or a.tile == 0:
-        # autotuner: times candidate (k_max, t) plans on the circuit's first gates
+        # autotuner: times candidate (k_max, t, low qubits) plans on the circuit's first gates
         t0 = time.perf_counter()
         best = Q.qs_autotune(n, Q.QS_C64, gl, Q.opts(strategy=a.strategy, renorm=1))
         tune_s = time.perf_counter() - t0
-        a.k_max, a.tile = best.k_max, best.tile_qubits
+        a.k_max, a.tile, a.low = best.k_max, best.tile_qubits, best.low_qubits
     t0 = time.perf_counter()
-    plan = Q.qs_contract(n, gl, Q.opts(k_max=a.k_max, tile_qubits=a.tile, strategy=a.strategy, renorm=1))
+    plan = Q.qs_contract(n, gl, Q.opts(k_max=a.k_max, tile_qubits=a.tile, low_qubits=a.low, strategy=a.strategy,
+                                       renorm=1))
     plan_s = time.perf_counter() - t0
     info = Q.qs_plan_info_get(plan)
     S = 8.0 * (1 << n)
@@ -298,7 +300,7 @@ def main():
         "data": "synthetic (seeded UCC-style Pauli-exponential circuit)",
         "config": {"workload": f"ucc n={n} n_exp={a.n_exp} seed={a.seed} complex64", "n_qubits": n,
                    "n_gates": int(info.n_gates), "n_blocks": int(info.n_blocks), "n_passes": int(info.n_passes),
-                   "k_max": a.k_max, "tile_qubits": a.tile, "strategy": a.strategy,
+                   "k_max": a.k_max, "tile_qubits": a.tile, "low_qubits": a.low, "strategy": a.strategy,
                    "flops_per_amp_dense_equiv": round(info.flops_per_amp / max(1, info.n_passes), 1)},
         "circuit_time_s": round(ms_step / 1e3, 4),
         "gates_per_s": round(info.n_gates / (ms_step / 1e3), 1),
@@ -313,7 +315,8 @@ def main():
         # the generator draws exponentials in order, so this is the circuit's prefix
         pre_gates, _ = qsynth.ucc(n, n_exp=a.plain_prefix, seed=a.seed)
         gl2 = Q.GateList(pre_gates)
-        plan2 = Q.qs_contract(n, gl2, Q.opts(k_max=a.k_max, tile_qubits=a.tile, strategy=a.strategy, renorm=1))
+        plan2 = Q.qs_contract(n, gl2, Q.opts(k_max=a.k_max, tile_qubits=a.tile, low_qubits=a.low,
+                                             strategy=a.strategy, renorm=1))
         info2 = Q.qs_plan_info_get(plan2)
         Q.qs_profile_enable(True)
         Q.qs_profile_collect()

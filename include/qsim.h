@@ -189,9 +189,10 @@ qs_status qs_batch_run(qs_batch b, double *energies);
 qs_status qs_batch_state_copy_out(qs_batch b, int i, double *host);
 
 /* -------------------------------------------------------------- tuning */
-/* Time candidate (k_max, t) pairs for this circuit on the device and return
- * the fastest in *best (strategy and renorm copied from base).  The circuit
- * runs on a scratch state of its own size.  Synchronous. */
+/* Time candidate (k_max, tile_qubits, low_qubits) triples for this circuit
+ * on the device and return the fastest in *best (strategy and renorm copied
+ * from base).  The circuit (its first 1536 gates when longer) runs on a
+ * scratch state of its own size.  Synchronous. */
 qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, size_t n_gates,
                       const qs_contract_opts *base, qs_contract_opts *best);
 

@@ -1,11 +1,15 @@
-// Autotuner: picks the fusion width k_max and tile size t for a circuit by
-// running candidate plans on the device and keeping the fastest.
+// Autotuner: picks the fusion width k_max, the tile size t and the number of
+// fixed contiguous low qubits per tile for a circuit by running candidate
+// plans on the device and keeping the fastest.
 //
-// Candidates are k_max in 2..5 crossed with t in {11, 12, 13} (capped by n and
-// by the dtype's LDS limit).  Each candidate's plan runs on a scratch state
-// once to warm up and is then timed with hipEvents; circuits longer than
-// kTunePrefix gates are tuned on their first kTunePrefix gates (the passes of a
-// long circuit repeat the same structure).  Results are cached per
+// Stage 1 crosses k_max in 3..5 with t in {11, 12, 13} (capped by n and by the
+// dtype's LDS limit) at 4 and 6 low qubits; stage 2 tries 3 and 5 low qubits
+// for the winning (k_max, t).  Fewer fixed low qubits leave more tile slots to
+// the qubits the gates touch (fewer passes) at the price of shorter coalesced
+// runs per tile segment.  Each candidate's plan runs on a scratch state once
+// to warm up and is then timed with hipEvents; circuits longer than
+// kTunePrefix gates are tuned on their first kTunePrefix gates (the passes of
+// a long circuit repeat the same structure).  Results are cached per
 // (n, dtype, strategy, gate structure) for the life of the process.
 #include <algorithm>
 #include <cstring>
@@ -18,7 +22,7 @@
 
 namespace {
 
-constexpr size_t kTunePrefix = 4096;
+constexpr size_t kTunePrefix = 1536;
 
 uint64_t structure_hash(const qs_gate *g, size_t n) {
     uint64_t h = 1469598103934665603ull;
@@ -61,19 +65,24 @@ extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, si
             return QS_OK;
         }
     }
-    const int kcap = dtype == QS_C128 ? 5 : 5;
     const int tcap = dtype == QS_C128 ? 12 : 13;
     int wmax = 1;
     for (size_t i = 0; i < ng; ++i) wmax = std::max(wmax, (int)gates[i].nq);
-    std::vector<std::pair<int, int>> cand;
-    for (int k = 2; k <= kcap; ++k)
-        for (int t = 11; t <= tcap; ++t) {
-            const int tt = std::min(t, n);
-            const int kk = std::min(k, n);
-            if (tt < n && std::max(kk, wmax) > tt - 1) continue;
-            if (std::find(cand.begin(), cand.end(), std::make_pair(kk, tt)) == cand.end()) cand.push_back({kk, tt});
-        }
-    if (cand.empty()) cand.push_back({std::min(2, n), std::min(tcap, n)});
+    struct Cand {
+        int k, t, low;
+        bool operator==(const Cand &o) const { return k == o.k && t == o.t && low == o.low; }
+    };
+    std::vector<Cand> cand;
+    auto add = [&](int k, int t, int low) {
+        const int tt = std::min(t, n), kk = std::min(k, n);
+        if (tt < n && std::max(kk, wmax) > tt - 1) return;
+        const Cand c{kk, tt, std::min(low, tt)};
+        if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    };
+    for (int k = 3; k <= 5; ++k)
+        for (int t = 11; t <= tcap; ++t)
+            for (int low : {4, 6}) add(k, t, low);
+    if (cand.empty()) cand.push_back({std::min(2, n), std::min(tcap, n), std::min(6, n)});
     qs_state s = nullptr;
     qs_status st = qs_state_create(n, dtype, nullptr, nullptr, &s);
     if (st != QS_OK) return st;
@@ -82,28 +91,37 @@ extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, si
     hipEventCreate(&e1);
     float best_ms = 1e30f;
     qs_contract_opts win = b;
-    win.k_max = cand[0].first;
-    win.tile_qubits = cand[0].second;
-    for (auto [k, t] : cand) {
-        qs_contract_opts o = b;
-        o.k_max = k;
-        o.tile_qubits = t;
-        qs_plan p = nullptr;
-        st = qs_contract(n, gates, ng, &o, &p);
-        if (st != QS_OK) continue;  // candidate not valid for this circuit
-        float ms = 0;
-        bool ok = qs_state_set_basis(s, 0) == QS_OK && qs_apply_plan(s, p) == QS_OK;
-        if (ok) {
-            hipEventRecord(e0, nullptr);
-            ok = qs_apply_plan(s, p) == QS_OK;
-            hipEventRecord(e1, nullptr);
-            ok = ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    win.k_max = cand[0].k;
+    win.tile_qubits = cand[0].t;
+    win.low_qubits = cand[0].low;
+    auto run = [&](size_t from) {
+        for (size_t i = from; i < cand.size(); ++i) {
+            qs_contract_opts o = b;
+            o.k_max = cand[i].k;
+            o.tile_qubits = cand[i].t;
+            o.low_qubits = cand[i].low;
+            qs_plan p = nullptr;
+            if (qs_contract(n, gates, ng, &o, &p) != QS_OK) continue;  // candidate not valid for this circuit
+            float ms = 0;
+            bool ok = qs_state_set_basis(s, 0) == QS_OK && qs_apply_plan(s, p) == QS_OK;
+            if (ok) {
+                hipEventRecord(e0, nullptr);
+                ok = qs_apply_plan(s, p) == QS_OK;
+                hipEventRecord(e1, nullptr);
+                ok = ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            }
+            qs_plan_destroy(p);
+            if (ok && ms < best_ms) {
+                best_ms = ms;
+                win = o;
+            }
         }
-        qs_plan_destroy(p);
-        if (ok && ms < best_ms) {
-            best_ms = ms;
-            win = o;
-        }
+    };
+    run(0);
+    if (best_ms < 1e30f) {
+        const size_t n1 = cand.size();
+        for (int low : {3, 5}) add(win.k_max, win.tile_qubits, low);
+        run(n1);
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -495,7 +495,7 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
         }
         b->plans.push_back(p);
         b->n.push_back(n_qubits[i]);
-        st = plan_upload(*p, dt);
+        st = plan_upload(*p, dt, false);
         if (st != QS_OK) return fail(st);
     }
     // ---- device layout ----

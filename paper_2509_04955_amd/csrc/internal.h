@@ -69,6 +69,8 @@ struct PassArgs {
     int32_t hi[kMaxTile];   // global qubit of tile position c + j (ascending)
     int32_t apply_scale;    // multiply amplitudes by *scale on load
     int32_t want_norm;      // write FP64 sum |a|^2 partial per tile
+    int32_t cl_off;         // block operands staged in LDS: pool elements
+    int32_t cl_len;         //   [cl_off, cl_off + cl_len), 0 = none
 };
 
 // --------------------------------------------------------------- state
@@ -126,6 +128,8 @@ struct qs_plan_s {
     void *d_pool[2] = {nullptr, nullptr};
     std::vector<qs::BlockDev> h_blocks[2];
     std::vector<uint8_t> pass_wide[2];  // pass needs the wide kernel variant
+    // pool range of the pass's block operands staged in LDS (len 0 = none)
+    std::vector<int32_t> pass_cl_off[2], pass_cl_len[2];
     ~qs_plan_s();
 };
 
@@ -137,10 +141,13 @@ qs_status make_gate(const qs_gate &g, int n, HGate &out);
 // planner.cpp
 qs_status build_plan(qs_plan_s &p);
 void block_matrix(const std::vector<HGate> &gates, HBlock &b);
-qs_status plan_upload(qs_plan_s &p, qs_dtype dt);
+// stage_lds: let passes stage their block operands in LDS (the single-state
+// pass kernel); the batch kernel reads them from the pool.
+qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds = true);
 // kernels_tile.hip: how the tile kernel will apply a block (BK_*); dest gets
-// the monomial destinations when the block is monomial
-int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest);
+// the monomial destinations when the block is monomial; lds: the pass stages
+// its operands in LDS (dense complex64 k = 3 then also runs on MFMA)
+int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds = false);
 void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
                  std::vector<HPass> &out);
 void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks);

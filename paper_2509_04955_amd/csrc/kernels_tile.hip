@@ -64,14 +64,27 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v) {
 // NJ = 0 handles any tile size; vectors beyond the prefetch depth are then
 // loaded in batches whose loads are all issued before the first of them is
 // waited on.
-template <typename R, bool WIDE, int NJ>
-__global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_tile_pass(
+// Waves per SIMD the register budget is sized for: complex64 tiles of up to
+// 2^12 amplitudes run 4 workgroups per CU; 2^13-amplitude complex64 tiles and
+// complex128 tiles are held to 2 per CU by LDS or registers anyway, so those
+// variants take twice the registers and prefetch the whole next tile.
+// With the pass's block operands staged in LDS (CL) a 2^12-amplitude
+// complex64 tile runs 3 workgroups per CU, leaving about 20 KB of LDS per
+// workgroup for the operands.
+template <typename R, bool WIDE, int NJ, bool CL>
+constexpr int tile_waves() {
+    return WIDE ? 1 : (sizeof(R) == 4 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
+}
+
+template <typename R, bool WIDE, int NJ, bool CL>
+__global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pass(
     typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
     const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials) {
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
-    constexpr int PF = NJ > 0 && NJ < kPrefetch ? NJ : kPrefetch;
+    constexpr int PFMAX = tile_waves<R, WIDE, NJ, CL>() <= 3 ? 16 : kPrefetch;
+    constexpr int PF = NJ > 0 ? (NJ < PFMAX ? NJ : PFMAX) : kPrefetch;
     constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *tile = reinterpret_cast<A *>(smem_raw);
@@ -97,7 +110,7 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
             v.w *= sc;
             *reinterpret_cast<float4 *>(tile + si) = v;
         } else {
-            double2 d = *reinterpret_cast<double2 *>(&v);
+            double2 d = __builtin_bit_cast(double2, v);
             d.x *= sc;
             d.y *= sc;
             tile[si] = d;
@@ -117,6 +130,14 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
     };
     uint64_t tileid = blockIdx.x;
     if (tileid >= ntiles) return;   // whole workgroup
+    // block operands of the pass -> LDS behind the tile (once per workgroup;
+    // pool entries are 16-byte aligned and cl_len a multiple of 16 bytes)
+    R *cst = reinterpret_cast<R *>(smem_raw + (size_t)tsize * sizeof(A));
+    if constexpr (CL) {
+        constexpr int EPV = 16 / sizeof(R);
+        for (int i = threadIdx.x * EPV; i < pa.cl_len; i += TT * EPV)
+            *reinterpret_cast<float4 *>(cst + i) = *reinterpret_cast<const float4 *>(pool + pa.cl_off + i);
+    }
     uint64_t base = tile_base(tileid, pa);
     if (active) {
 #pragma unroll
@@ -154,7 +175,7 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
         }
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
-            apply_block<R, WIDE>(tile, T, blocks + pa.block0 + b, pool);
+            apply_block<R, WIDE, CL>(tile, T, blocks + pa.block0 + b, pool, cst, pa.cl_off);
             __syncthreads();
         }
         float4 ex[EX > 0 ? EX : 1];
@@ -166,12 +187,15 @@ __global__ __launch_bounds__(TT, WIDE ? 1 : (sizeof(R) == 4 ? 4 : 2)) void k_til
         double nacc = 0.0;
         if (active) {
             for (uint32_t j = 0; j < nj; ++j) {
+                // keep the scheduler from hoisting every LDS read of the
+                // store phase ahead of the stores (register pressure)
+                if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
                 const float4 v = *reinterpret_cast<const float4 *>(tile + (s_t ^ sw(j * TT * APV)));
                 st_nt(const_cast<float4 *>(gaddr(base, j)), v);
                 if constexpr (F32) {
                     nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
                 } else {
-                    const double2 d = *reinterpret_cast<const double2 *>(&v);
+                    const double2 d = __builtin_bit_cast(double2, v);
                     nacc += d.x * d.x + d.y * d.y;
                 }
             }
@@ -247,23 +271,41 @@ template <typename R>
 using TileKernel = void (*)(typename AmpOf<R>::A *, uint64_t, PassArgs, const BlockDev *, const R *, const double *,
                             double *);
 
-// Kernel variant for a pass: register footprint (wide) and, for the common
-// tile sizes of the narrow variant, the compile-time vector count.
+// Kernel variant for a pass: register footprint (wide), LDS-staged operands
+// (cl) and, for the narrow variant, the compile-time vector count.
 template <typename R>
-TileKernel<R> pick_tile_kernel(bool wide, int t) {
+TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl) {
     constexpr int APV = sizeof(R) == 4 ? 2 : 1;
     const int vpt = (1 << t) / (TT * APV);   // 16-byte vectors per thread
-    if (wide) return k_tile_pass<R, true, 0>;
+    if (wide) return k_tile_pass<R, true, 0, false>;
     if ((1 << t) == vpt * TT * APV) {
         if constexpr (sizeof(R) == 4) {
-            if (vpt == 4) return k_tile_pass<R, false, 4>;
-            if (vpt == 8) return k_tile_pass<R, false, 8>;
-        } else {
-            if (vpt == 8) return k_tile_pass<R, false, 8>;
-            if (vpt == 16) return k_tile_pass<R, false, 16>;
+            if (cl) {
+                if (vpt == 4) return k_tile_pass<R, false, 4, true>;
+                if (vpt == 8) return k_tile_pass<R, false, 8, true>;
+                if (vpt == 16) return k_tile_pass<R, false, 16, true>;
+            }
         }
+        if (vpt == 1) return k_tile_pass<R, false, 1, false>;
+        if (vpt == 2) return k_tile_pass<R, false, 2, false>;
+        if (vpt == 4) return k_tile_pass<R, false, 4, false>;
+        if (vpt == 8) return k_tile_pass<R, false, 8, false>;
+        if (vpt == 16) return k_tile_pass<R, false, 16, false>;
     }
-    return k_tile_pass<R, false, 0>;
+    return k_tile_pass<R, false, 0, false>;
+}
+
+// LDS bytes a pass may use for staged operands: what is left of the CU's LDS
+// share per workgroup at the occupancy the staged variant targets (2^11: 4,
+// 2^12: 3, 2^13: 2 workgroups per CU), minus the tile and a margin for the
+// kernel's static LDS.  0 = no staged variant for this tile.
+size_t lds_operand_budget(int t, qs_dtype dt) {
+    if (dt != QS_C64) return 0;
+    constexpr size_t kLds = 160 * 1024, kMargin = 512;
+    const int wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : 0;
+    if (!wgs) return 0;
+    const size_t share = (kLds / wgs) & ~(size_t)1023, tile = (size_t)8 << t;
+    return share > tile + kMargin ? share - tile - kMargin : 0;
 }
 
 // Raise a kernel's dynamic LDS limit once per (kernel, size).
@@ -290,9 +332,15 @@ bool mfma_enabled() {
     return v == 1;
 }
 
-// Host-side A-operand swizzle of a complex64 block for mfma_block<K>.
-void swizzle_mfma(const std::vector<cd> &U, int k, std::vector<float> &out) {
+// Host-side A-operand swizzle of a complex64 block: entry (R, kk) of the
+// real embedding [[Ur, -Ui], [Ui, Ur]] for M-tile mt, step s and lane l is row
+// R = 16 mt + l % 16 and input (row 4 (s / 2) + l / 16, part s % 2).
+// Layout [mt][s][lane] for mfma_block, [mt][s / 4][lane][s % 4] for
+// mfma_block_lds (16-byte LDS reads).
+void swizzle_mfma(const std::vector<cd> &U, int k, bool lds_layout, std::vector<float> &out) {
     const int D = 1 << k, MT = 2 * D / 16, S = 2 * D / 4;
+    const size_t o0 = out.size();
+    out.resize(o0 + (size_t)MT * S * 64);
     for (int mt = 0; mt < MT; ++mt)
         for (int s = 0; s < S; ++s)
             for (int lane = 0; lane < 64; ++lane) {
@@ -304,7 +352,9 @@ void swizzle_mfma(const std::vector<cd> &U, int k, std::vector<float> &out) {
                 double v;
                 if (ro == 0) v = p == 0 ? u.real() : -u.imag();
                 else v = p == 0 ? u.imag() : u.real();
-                out.push_back((float)v);
+                const size_t idx = lds_layout ? (((size_t)mt * (S / 4) + s / 4) * 64 + lane) * 4 + s % 4
+                                              : ((size_t)mt * S + s) * 64 + lane;
+                out[o0 + idx] = (float)v;
             }
 }
 
@@ -335,12 +385,20 @@ bool structured_enabled() {
     return v == 1;
 }
 
+bool staged_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_TILE_STAGED");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v == 1;
+}
+
 template <typename R>
-void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<R> &pool, bool &wide) {
+void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, std::vector<R> &pool, bool &wide) {
     const int D = 1 << d.k;
     std::vector<int> dest;
-    const bool f32 = dt == QS_C64;
-    const int kind = block_kind(blk, t, dt, &dest);
+    const int kind = block_kind(blk, t, dt, &dest, lds);
     if (kind == BK_MONO) {
         d.kind = BK_MONO;
         d.mat_off = (int32_t)pool.size();
@@ -355,12 +413,11 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<
             pool.push_back((R)0);
         }
     } else if (kind == BK_MFMA) {
-        (void)f32;
         d.kind = BK_MFMA;
         d.mat_off = (int32_t)pool.size();
-        std::vector<float> sw;
-        swizzle_mfma(blk.U, d.k, sw);
-        for (float v : sw) pool.push_back((R)v);
+        std::vector<float> a;
+        swizzle_mfma(blk.U, d.k, lds, a);
+        for (float v : a) pool.push_back((R)v);
     } else {
         d.kind = BK_DENSE;
         d.mat_off = (int32_t)pool.size();
@@ -371,6 +428,20 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, std::vector<
         if (d.k > 3) wide = true;
     }
     while (pool.size() % 4) pool.push_back((R)0);  // 16-byte aligned entries
+}
+
+// Pool bytes the blocks of a pass take when staged (the kinds of a staged pass).
+size_t pass_operand_bytes(const qs_plan_s &p, const HPass &ps, qs_dtype dt) {
+    size_t b = 0;
+    for (int64_t i = ps.block0; i < ps.block0 + ps.nblocks; ++i) {
+        const HBlock &blk = p.blocks[i];
+        const int k = (int)blk.qubits.size(), D = 1 << k;
+        const int kind = block_kind(blk, ps.t, dt, nullptr, true);
+        size_t e = kind == BK_MONO ? 4 * (size_t)D : kind == BK_MFMA ? (size_t)4 * D * D : 2 * (size_t)D * D;
+        e = (e + 3) / 4 * 4;
+        b += e * (dt == QS_C64 ? 4 : 8);
+    }
+    return b;
 }
 
 // Workgroups of a tile kernel resident at once on the current device.
@@ -392,24 +463,41 @@ uint64_t resident_groups(const void *fn, size_t lds) {
 
 }  // namespace
 
-int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest) {
+int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds) {
     const int k = (int)b.qubits.size();
     std::vector<int> tmp;
     if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp)) return BK_MONO;
-    if (dt == QS_C64 && (k == 4 || k == 5) && t - k >= 4 && mfma_enabled()) return BK_MFMA;
+    if (dt == QS_C64 && (k == 4 || k == 5 || (lds && k == 3)) && t - k >= 4 && mfma_enabled()) return BK_MFMA;
     return BK_DENSE;
 }
 
-qs_status plan_upload(qs_plan_s &p, qs_dtype dt) {
+qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
     const int di = dt == QS_C64 ? 0 : 1;
     if (p.dev_ready[di]) return QS_OK;
     std::vector<BlockDev> hb(p.blocks.size());
     std::vector<float> pool32;
     std::vector<double> pool64;
     p.pass_wide[di].assign(p.passes.size(), 0);
+    p.pass_cl_off[di].assign(p.passes.size(), 0);
+    p.pass_cl_len[di].assign(p.passes.size(), 0);
     for (size_t pi = 0; pi < p.passes.size(); ++pi) {
         const HPass &ps = p.passes[pi];
         bool wide = false;
+        // stage the pass's operands in LDS when they fit and the pass has
+        // blocks that read per-lane operands (MFMA, wide monomial)
+        bool lds = false;
+        if (stage_lds && staged_enabled()) {
+            const size_t budget = lds_operand_budget(ps.t, dt);
+            bool per_lane = false, dense_wide = false;
+            for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
+                const int k = (int)p.blocks[b].qubits.size();
+                const int kind = block_kind(p.blocks[b], ps.t, dt, nullptr, true);
+                per_lane |= kind == BK_MFMA || (kind == BK_MONO && k >= 4);
+                dense_wide |= kind == BK_DENSE && k > 3;
+            }
+            lds = budget && per_lane && !dense_wide && pass_operand_bytes(p, ps, dt) <= budget;
+        }
+        const size_t pool0 = dt == QS_C64 ? pool32.size() : pool64.size();
         for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
             const HBlock &blk = p.blocks[b];
             BlockDev &d = hb[b];
@@ -419,10 +507,15 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt) {
                      "block width %d unsupported for this dtype", d.k);
             for (int j = 0; j < d.k; ++j)
                 d.pos[j] = (int)(std::find(ps.tile.begin(), ps.tile.end(), blk.qubits[j]) - ps.tile.begin());
-            if (dt == QS_C64) push_block<float>(blk, d, ps.t, dt, pool32, wide);
-            else push_block<double>(blk, d, ps.t, dt, pool64, wide);
+            if (dt == QS_C64) push_block<float>(blk, d, ps.t, dt, lds, pool32, wide);
+            else push_block<double>(blk, d, ps.t, dt, lds, pool64, wide);
         }
         p.pass_wide[di][pi] = wide ? 1 : 0;
+        if (lds) {
+            const size_t pool1 = dt == QS_C64 ? pool32.size() : pool64.size();
+            p.pass_cl_off[di][pi] = (int32_t)pool0;
+            p.pass_cl_len[di][pi] = (int32_t)(pool1 - pool0);
+        }
     }
     p.h_blocks[di] = hb;
     const size_t bbytes = std::max<size_t>(1, hb.size()) * sizeof(BlockDev);
@@ -462,6 +555,9 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     for (int j = 0; j < ps.t - ps.c; ++j) pa.hi[j] = ps.tile[ps.c + j];
     pa.apply_scale = scale_in ? 1 : 0;
     pa.want_norm = want_norm ? 1 : 0;
+    pa.cl_off = p.pass_cl_off[di][pass_index];
+    pa.cl_len = p.pass_cl_len[di][pass_index];
+    const bool cl = pa.cl_len > 0;
     const uint64_t ntiles = 1ull << (s.n - ps.t);
     if (want_norm) {
         qs_status st = ensure_partials(s, ntiles);
@@ -472,9 +568,9 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     // loads in flight while the current one is processed
     const bool wide = p.pass_wide[di][pass_index] != 0;
     const size_t amp = s.dtype == QS_C64 ? 8 : 16;
-    const size_t lds = amp << ps.t;
-    const void *fn = s.dtype == QS_C64 ? reinterpret_cast<const void *>(pick_tile_kernel<float>(wide, ps.t))
-                                       : reinterpret_cast<const void *>(pick_tile_kernel<double>(wide, ps.t));
+    const size_t lds = (amp << ps.t) + (size_t)pa.cl_len * (s.dtype == QS_C64 ? 4 : 8);
+    const void *fn = s.dtype == QS_C64 ? reinterpret_cast<const void *>(pick_tile_kernel<float>(wide, ps.t, cl))
+                                       : reinterpret_cast<const void *>(pick_tile_kernel<double>(wide, ps.t, cl));
     const uint64_t resident = resident_groups(fn, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
     const double S = std::ldexp((double)amp, s.n);
@@ -484,10 +580,10 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
                  std::ldexp(1.0, s.n);
     prof_begin(s.stream, QS_PROF_TILE, 2 * S, flops);
     if (s.dtype == QS_C64)
-        hipLaunchKernelGGL(pick_tile_kernel<float>(wide, ps.t), grid, dim3(TT), lds, s.stream, (float2 *)s.amp, ntiles,
+        hipLaunchKernelGGL(pick_tile_kernel<float>(wide, ps.t, cl), grid, dim3(TT), lds, s.stream, (float2 *)s.amp, ntiles,
                            pa, p.d_blocks[di], (const float *)p.d_pool[di], s.d_slots + 1, s.d_partials);
     else
-        hipLaunchKernelGGL(pick_tile_kernel<double>(wide, ps.t), grid, dim3(TT), lds, s.stream, (double2 *)s.amp,
+        hipLaunchKernelGGL(pick_tile_kernel<double>(wide, ps.t, cl), grid, dim3(TT), lds, s.stream, (double2 *)s.amp,
                            ntiles, pa, p.d_blocks[di], (const double *)p.d_pool[di], s.d_slots + 1, s.d_partials);
     prof_end(s.stream);
     QS_HIP(hipGetLastError());

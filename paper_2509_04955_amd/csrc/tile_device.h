@@ -311,21 +311,124 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
     }
 }
 
+// ---- MFMA block with the A operand in LDS (complex64, K = 3, 4, 5) --------
+// The same real GEMM as mfma_block, organised for a pass whose block operands
+// were staged in LDS: each wave owns whole 16-column chunks and runs every
+// M-tile over them, re-reading A from LDS (16-byte reads, layout
+// [M-tile][step/4][lane][4]).  A chunk's inputs are all in registers before
+// any of its outputs is written and no other wave touches the chunk, so the
+// block needs no barrier of its own.  Output row R = 16 m + 4 (lane/16) + q is
+// amplitude R mod 2^K, real part when R < 2^K (K = 3 has one M-tile holding
+// both parts).  CPI chunks are in flight per wave (CPI * MT accumulator
+// chains).
+template <int K>
+__device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockDev *bd, const float *As) {
+    constexpr int D = 1 << K;
+    constexpr int MT = 2 * D / 16;
+    constexpr int S = 2 * D / 4;
+    constexpr int NB = D / 4;
+    constexpr int CPI = K >= 5 ? 1 : 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gq = lane >> 4, jc = lane & 15;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    auto deposit = [&](int r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if ((r >> j) & 1) o |= 1u << pos[j];
+        return o;
+    };
+    uint32_t offB[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq));
+    // float index of output (m, q) relative to 2 * (chunk column base):
+    // 2 * sw(row offset) | part
+    uint32_t oc[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int R = 16 * m + 4 * gq + q;
+            oc[m][q] = (2u * sw(deposit(R % D))) | (uint32_t)(R / D);
+        }
+    float *tf = reinterpret_cast<float *>(tile);
+    const floatx4 *A4 = reinterpret_cast<const floatx4 *>(As);
+    const uint32_t nchunks = (1u << (T - K)) / 16;
+    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += 4 * CPI) {
+        uint32_t cb[CPI];
+        float2 bv[CPI][NB];
+#pragma unroll
+        for (int h = 0; h < CPI; ++h) {
+            const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
+            uint32_t c = ch * 16 + jc;
+#pragma unroll
+            for (int j = 0; j < K; ++j) c = ins0_32(c, pos[j]);
+            cb[h] = sw(c);
+#pragma unroll
+            for (int m = 0; m < NB; ++m) bv[h][m] = tile[cb[h] ^ offB[m]];
+        }
+        floatx4 acc[CPI][MT];
+#pragma unroll
+        for (int h = 0; h < CPI; ++h)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[h][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s4 = 0; s4 < S / 4; ++s4) {
+            floatx4 a[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) a[m] = A4[(m * (S / 4) + s4) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int s = 4 * s4 + u;
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int h = 0; h < CPI; ++h)
+                        acc[h][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            a[m][u], (s & 1) ? bv[h][s >> 1].y : bv[h][s >> 1].x, acc[h][m], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < CPI; ++h) {
+            if (ch0 + h < nchunks) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tf[(2u * cb[h]) ^ oc[m][q]] = acc[h][m][q];
+            }
+        }
+    }
+}
+
 // ---- the pass kernel ------------------------------------------------------
 // WIDE = false keeps register use low (dense VALU blocks up to k = 3, complex64
 // dense k = 4, 5 through MFMA, monomial blocks of any width); WIDE = true adds
 // dense VALU blocks with k >= 4.  The host picks the variant per pass.
-template <typename R, bool WIDE>
+// CL = true: the pass's block operands were staged in LDS at `cst` (pool
+// element cl_off is cst[0]); complex64 MFMA blocks (k = 3, 4, 5) and monomial
+// blocks with k >= 4 (per-lane records) read them there, dense VALU blocks and
+// narrow monomial blocks keep their wave-uniform scalar loads from the pool.
+template <typename R, bool WIDE, bool CL = false>
 __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                            const R *__restrict__ pool) {
+                                            const R *__restrict__ pool, const R *cst = nullptr, int cl_off = 0) {
     const int k = bd->k;
     const int kind = bd->kind;
     const R *U = pool + bd->mat_off;
     constexpr bool F32 = sizeof(R) == 4;
     if constexpr (F32) {
         if (kind == BK_MFMA) {
-            if (k == 4) mfma_block<4>(tile, T, bd, U);
-            else mfma_block<5>(tile, T, bd, U);
+            if constexpr (CL) {
+                const float *As = cst + (bd->mat_off - cl_off);
+                if (k == 3) mfma_block_lds<3>(tile, T, bd, As);
+                else if (k == 4) mfma_block_lds<4>(tile, T, bd, As);
+                else mfma_block_lds<5>(tile, T, bd, As);
+            } else {
+                if (k == 4) mfma_block<4>(tile, T, bd, U);
+                else mfma_block<5>(tile, T, bd, U);
+            }
             return;
         }
     }
@@ -334,9 +437,21 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
         case 1: mono_block<1, R>(tile, T, bd, U); return;
         case 2: mono_block<2, R>(tile, T, bd, U); return;
         case 3: mono_block<3, R>(tile, T, bd, U); return;
-        case 4: mono_block<4, R>(tile, T, bd, U); return;
-        case 5: mono_block<5, R>(tile, T, bd, U); return;
-        default: mono_block<6, R>(tile, T, bd, U); return;
+        default: break;
+        }
+        if constexpr (CL) {
+            const R *E = cst + (bd->mat_off - cl_off);
+            switch (k) {
+            case 4: mono_block<4, R>(tile, T, bd, E); return;
+            case 5: mono_block<5, R>(tile, T, bd, E); return;
+            default: mono_block<6, R>(tile, T, bd, E); return;
+            }
+        } else {
+            switch (k) {
+            case 4: mono_block<4, R>(tile, T, bd, U); return;
+            case 5: mono_block<5, R>(tile, T, bd, U); return;
+            default: mono_block<6, R>(tile, T, bd, U); return;
+            }
         }
     }
     switch (k) {

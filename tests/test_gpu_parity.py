@@ -102,10 +102,11 @@ def test_plain_dense_gates(Q, oracle, dtype, tol):
 
 
 @pytest.mark.parametrize("k_max", [1, 2, 3, 4, 5])
-@pytest.mark.parametrize("t", [6, 9, 13])
+@pytest.mark.parametrize("t", [6, 9, 10, 11, 12, 13])
 def test_fused_c64_random(Q, oracle, k_max, t):
     """Fused tile passes, complex64: VALU blocks (k <= 3) and MFMA blocks
-    (k = 4, 5) over several tiles and ragged pass boundaries."""
+    (k = 4, 5) over several tiles and ragged pass boundaries; every tile size
+    from a partial workgroup (t = 6) to 16 vectors per thread (t = 13)."""
     n = 14
     if k_max > t - 1:
         pytest.skip("block wider than tile")
@@ -119,7 +120,7 @@ def test_fused_c64_random(Q, oracle, k_max, t):
 
 
 @pytest.mark.parametrize("k_max", [1, 3, 5])
-@pytest.mark.parametrize("t", [7, 12])
+@pytest.mark.parametrize("t", [7, 8, 9, 10, 11, 12])
 def test_fused_c128_random(Q, oracle, k_max, t):
     n = 13
     c = qsynth.random_circuit(n, 250, seed=20 + k_max, max_dense=2)
@@ -127,6 +128,50 @@ def test_fused_c128_random(Q, oracle, k_max, t):
     ref = oracle.run(c, psi0.copy())
     got, _ = run_plan(Q, c, Q.QS_C128, psi0, k_max=k_max, tile_qubits=t)
     assert oracle.max_abs(ref, got) <= TOL128
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("low", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("t", [11, 12, 13])
+def test_fused_low_qubit_counts(Q, oracle, dtype, low, t):
+    """Tiles with 1..5 fixed contiguous low qubits (shorter coalesced runs,
+    more free high-qubit slots) give the same state."""
+    if dtype == 1 and t > 12:
+        pytest.skip("complex128 tiles stop at t = 12")
+    n = 15
+    c, _ = qsynth.ucc(n, 12, seed=50 + low)
+    psi0 = qsynth.random_state(n, seed=9)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=4, tile_qubits=t, low_qubits=low)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
+@pytest.mark.parametrize("n5,n3", [(1, 2), (0, 6), (3, 0), (2, 3)])
+@pytest.mark.parametrize("t", [11, 12, 13])
+def test_fused_mfma_operands_staged_or_not(Q, oracle, n5, n3, t):
+    """Passes whose MFMA operands fit the LDS left beside the tile (one dense
+    5-qubit block = 16 KB, 3-qubit blocks 1 KB each) stage them there and also
+    run 3-qubit blocks on MFMA; passes over the budget (several 5-qubit
+    blocks) read them from the pool.  Both give the oracle's state."""
+    n = 15
+    rng = np.random.default_rng(100 * n5 + n3 + t)
+
+    def unitary(k):
+        a = rng.normal(size=(1 << k, 1 << k)) + 1j * rng.normal(size=(1 << k, 1 << k))
+        return np.linalg.qr(a)[0]
+
+    c = qsynth.Circuit(n)
+    hi = list(range(6, n))
+    for _ in range(2):
+        for k, cnt in ((5, n5), (3, n3)):
+            for _ in range(cnt):
+                qs = sorted(int(x) for x in rng.choice(list(range(6)) + hi[: t - 6], size=k, replace=False))
+                c.add("dense", qs, (), unitary(k))
+    psi0 = qsynth.random_state(n, seed=11)
+    ref = oracle.run(c, psi0.copy())
+    got, nrm = run_plan(Q, c, Q.QS_C64, psi0, k_max=5, tile_qubits=t)
+    assert oracle.max_abs(ref, got) <= TOL64
+    assert 1 - oracle.fidelity(ref, got) <= 1e-6
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
