@@ -11,8 +11,14 @@ and run the whole contracted circuit (every tile pass with its FP64
 renormalisation); the contraction plan (host) is built once before timing and
 its time is reported separately.
 
-Prints one JSON line.  `value` is the effective HBM bandwidth of the fused
-circuit: (passes * 2 * S + S) / step time, S = state bytes.
+Prints one JSON line.  `value` is the effective bandwidth of the fused
+circuit: the bytes the gate-by-gate method must stream for the same circuit
+(per gate 2S for a general or diagonal 1-qubit gate, S for a phase gate,
+CNOT-type or SWAP, S/2 for CZ-type; S = state bytes) divided by the circuit
+time.  The plain method's own effective bandwidth uses the same numerator, so
+the ratio of the two is the speedup.  `streamed_gbs` is what the fused passes
+actually move, (passes * 2 * S + S) / step time, and `roofline` is the tile
+kernel against the HBM (or MFMA) peak.
 """
 from __future__ import annotations
 
@@ -28,8 +34,40 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
-VALU_FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop x 2.4 GHz (no packed FP32)
+VALU_FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 METRIC = "circuit wall time + effective HBM GB/s at 30q fp32; fused vs gate-by-gate"
+
+
+# bytes one gate costs the gate-by-gate method (multiples of the state size),
+# following which plain kernel the library launches for it
+PLAIN_BYTES = {"z": 1.0, "s": 1.0, "sdg": 1.0, "t": 1.0, "tdg": 1.0, "p": 1.0, "cx": 1.0, "cu": 1.0,
+               "swap": 1.0, "cz": 0.5, "cp": 0.5}
+
+
+def plain_bytes(circ, S):
+    return sum(PLAIN_BYTES.get(g.name, 2.0) for g in circ.gates) * S
+
+
+def measured_traffic(n_qubits):
+    """HBM bytes per tile-pass launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE x 2 + WRITE_SIZE x 1, copy-kernel calibrated), or None
+    when the tile-kernel sources changed since the counters were taken or the
+    workload is not the profiled 30-qubit one."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_counters_ucc30.md")
+    if n_qubits != 30 or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_t = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    m_f = re.search(r"^kernel_source_fingerprint:\s*([0-9a-f]+)", text, re.M)
+    if not m_t or not m_f:
+        return None
+    h = hashlib.sha256()
+    for f in ("kernels_tile.hip", "tile_device.h", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2509_04955_amd", "csrc", f), "rb").read())
+    return int(m_t.group(1)) if h.hexdigest()[:16] == m_f.group(1) else None
 
 
 def parse():
@@ -163,17 +201,24 @@ def learned_mode(a):
     corr = float(np.corrcoef(CM.predict(X), y)[0, 1])
     c = qsynth.random_u3_cnot(n, 30, seed=5)
     gl = Q.GateList(c)
+    # the greedy reference gets its best fixed configuration (autotuned);
+    # the learned partition works inside the same tile shape
     t0 = time.perf_counter()
-    greedy = Q.qs_contract(n, gl, Q.opts(k_max=5, tile_qubits=13))
+    best = Q.qs_autotune(n, Q.QS_C64, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
+    tune_s = time.perf_counter() - t0
+    kw = dict(k_max=best.k_max, tile_qubits=best.tile_qubits, low_qubits=best.low_qubits)
+    t0 = time.perf_counter()
+    greedy = Q.qs_contract(n, gl, Q.opts(**kw))
     tg_plan = time.perf_counter() - t0
     t0 = time.perf_counter()
-    learned = Q.qs_contract(n, gl, Q.opts(k_max=5, tile_qubits=13, strategy=Q.STRATEGY_LEARNED))
+    learned = Q.qs_contract(n, gl, Q.opts(strategy=Q.STRATEGY_LEARNED, **kw))
     tl_plan = time.perf_counter() - t0
     ig, il = Q.qs_plan_info_get(greedy), Q.qs_plan_info_get(learned)
     st = Q.State(n, Q.QS_C64)
     ms_g = _timed(lambda: (st.set_basis(0), st.apply_plan(greedy)))
     ms_l = _timed(lambda: (st.set_basis(0), st.apply_plan(learned)))
-    out = {"mode": "learned", "n": n, "gates": len(c), "train_rows": int(len(y)), "train_loss": loss,
+    out = {"mode": "learned", "n": n, "gates": len(c), "greedy_config": kw, "autotune_s": round(tune_s, 1),
+           "train_rows": int(len(y)), "train_loss": loss,
            "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
            "greedy": {"passes": int(ig.n_passes), "blocks": int(ig.n_blocks), "ms": round(ms_g, 2),
                       "plan_s": round(tg_plan, 2)},
@@ -206,7 +251,9 @@ def brickwork_mode(a):
         S = (8 if dt == Q.QS_C64 else 16) * (1 << n)
         out[name] = {"plain_ms": round(ms_plain, 2), "fused_ms": round(ms_fused, 2),
                      "speedup": round(ms_plain / ms_fused, 2), "passes": int(info.n_passes),
-                     "fused_effective_gbs": round((info.n_passes * 2 + 1) * S / (ms_fused * 1e-3) / 1e9, 1)}
+                     "plain_effective_gbs": round(plain_bytes(c, S) / (ms_plain * 1e-3) / 1e9, 1),
+                     "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1),
+                     "fused_streamed_gbs": round((info.n_passes * 2 + 1) * S / (ms_fused * 1e-3) / 1e9, 1)}
         st.close()
         Q.qs_plan_destroy(plan)
     print(json.dumps(out), flush=True)
@@ -270,7 +317,8 @@ def main():
     Q.qs_profile_enable(False)
     ms_step = total_ms / a.steps
     alg_bytes = info.n_passes * 2 * S + S
-    value = alg_bytes / (ms_step * 1e-3) / 1e9
+    streamed = alg_bytes / (ms_step * 1e-3) / 1e9
+    value = plain_bytes(circ, S) / (ms_step * 1e-3) / 1e9
     nrm = st.norm()
 
     # dominant kernel: tile pass (per-launch averages from HIP events)
@@ -287,7 +335,7 @@ def main():
         roof = {"bound": "hbm", "achieved": tile_bytes / (tile_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(n)
     roof["kernel"] = "k_tile_pass<float>"
     roof["avg_launch_ms"] = tile_ms
     roof["hbm_gbs"] = tile_bytes / (tile_ms * 1e-3) / 1e9
@@ -303,6 +351,7 @@ def main():
                    "k_max": a.k_max, "tile_qubits": a.tile, "low_qubits": a.low, "strategy": a.strategy,
                    "flops_per_amp_dense_equiv": round(info.flops_per_amp / max(1, info.n_passes), 1)},
         "circuit_time_s": round(ms_step / 1e3, 4),
+        "streamed_gbs": round(streamed, 1),
         "gates_per_s": round(info.n_gates / (ms_step / 1e3), 1),
         "plan_time_s": round(plan_s, 3),
         "autotune_s": round(tune_s, 2),
@@ -347,6 +396,9 @@ def main():
             "plain_gates_per_s": round(info2.n_gates / (plain_ms / 1e3), 1),
             "plain_effective_gbs": round(pp.bytes[Q.PROF_PLAIN] / (pp.ms[Q.PROF_PLAIN] * 1e-3) / 1e9, 1)
             if pp.ms[Q.PROF_PLAIN] > 0 else None,
+            "fused_effective_gbs": round(plain_bytes(pre_gates, S) / (fused_ms * 1e-3) / 1e9, 1),
+            # the byte table above against the library's own count for the prefix
+            "plain_bytes_table_vs_library": round(plain_bytes(pre_gates, S) / max(1.0, pp.bytes[Q.PROF_PLAIN]), 6),
             "plain_extrapolated_circuit_s": round(plain_ms / 1e3 * info.n_gates / info2.n_gates, 2),
         }
     st.close()
@@ -369,11 +421,11 @@ def main():
         per_gate = cpu_s / len(gates)
         cpu_circuit_s = per_gate * info.n_gates
         out["cpu_baseline"] = {
-            "value": round(alg_bytes / cpu_circuit_s / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "value": round(plain_bytes(circ, S) / cpu_circuit_s / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {len(gates)} gates of the same circuit at n={n}, FP64 gate-by-gate "
                       f"({cpu_s:.1f} s); extrapolated linearly to {info.n_gates} gates = {cpu_circuit_s:.0f} s; "
-                      "value = the fused circuit's algorithmic bytes / extrapolated oracle time",
+                      "value = the circuit's gate-by-gate bytes / extrapolated oracle time",
             "gates_per_s": round(1.0 / per_gate, 3),
         }
     print(json.dumps(out), flush=True)

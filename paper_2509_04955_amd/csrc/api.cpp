@@ -350,11 +350,12 @@ qs_status qs_apply_plan(qs_state s, qs_plan p) {
     const bool renorm = p->opts.renorm != 0;
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const HPass &ps = p->passes[i];
-        st = launch_pass(*s, *p, ps, (int64_t)i, s->scale_pending, renorm);
+        uint64_t nparts = 0;
+        st = launch_pass(*s, *p, ps, (int64_t)i, s->scale_pending, renorm, &nparts);
         if (st != QS_OK) return st;
         s->scale_pending = false;
         if (renorm) {
-            st = launch_norm_reduce(*s, 1ull << (s->n - ps.t), s->d_slots);
+            st = launch_norm_reduce(*s, nparts, s->d_slots);
             if (st != QS_OK) return st;
             s->scale_pending = true;
         }

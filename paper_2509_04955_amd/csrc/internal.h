@@ -171,8 +171,9 @@ qs_status launch_scale(qs_state_s &s, const double *d_scale);
 qs_status launch_set_basis(qs_state_s &s, uint64_t index);
 qs_status launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
 // kernels_tile.hip
+// nparts (optional) receives the number of FP64 norm partials the pass wrote
 qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &pass, int64_t pass_index, bool scale_in,
-                      bool want_norm);
+                      bool want_norm, uint64_t *nparts = nullptr);
 qs_status launch_norm_reduce(qs_state_s &s, uint64_t nparts, double *d_out_slots);
 qs_status launch_norm_full(qs_state_s &s, double *d_out_slots);
 qs_status ensure_partials(qs_state_s &s, size_t count);

@@ -20,8 +20,9 @@
 //     per v_mfma_f32_16x16x4f32 chain, FP32 accumulation.  The A operand is
 //     pre-swizzled on the host so each lane loads its 4^(k+1)/64 values once.
 //   * Renormalisation: a pass multiplies by the previous pass's 1/sqrt(N) on
-//     load and emits one FP64 partial of sum |a|^2 per tile on store; a single
-//     workgroup then reduces the partials in a fixed order (deterministic).
+//     load and accumulates sum |a|^2 in FP64 on store, one partial per
+//     workgroup over its tiles in tile order; a single workgroup then sums the
+//     partials in a fixed order (deterministic for a given grid).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -129,7 +130,11 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
         }
     };
     uint64_t tileid = blockIdx.x;
-    if (tileid >= ntiles) return;   // whole workgroup
+    if (tileid >= ntiles) {   // whole workgroup
+        if (pa.want_norm && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
+    double wg_norm = 0.0;   // thread 0: this workgroup's tiles, in tile order
     // block operands of the pass -> LDS behind the tile (once per workgroup;
     // pool entries are 16-byte aligned and cl_len a multiple of 16 bytes)
     R *cst = reinterpret_cast<R *>(smem_raw + (size_t)tsize * sizeof(A));
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
                 double s = 0;
 #pragma unroll
                 for (int w = 0; w < TT / 64; ++w) s += red[w];
-                partials[tileid] = s;
+                wg_norm += s;
             }
         }
         __syncthreads();  // every read of this tile from LDS is done
@@ -228,6 +233,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
         tileid = nxt;
         base = nbase;
     }
+    if (pa.want_norm && threadIdx.x == 0) partials[blockIdx.x] = wg_norm;
 }
 
 // one workgroup: fixed-order FP64 sum of the partials; slot[0] = N, slot[1] = 1/sqrt(N)
@@ -544,7 +550,7 @@ qs_status ensure_partials(qs_state_s &s, size_t count) {
 }
 
 qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_t pass_index, bool scale_in,
-                      bool want_norm) {
+                      bool want_norm, uint64_t *nparts) {
     const int di = s.dtype == QS_C64 ? 0 : 1;
     PassArgs pa;
     std::memset(&pa, 0, sizeof pa);
@@ -559,10 +565,6 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     pa.cl_len = p.pass_cl_len[di][pass_index];
     const bool cl = pa.cl_len > 0;
     const uint64_t ntiles = 1ull << (s.n - ps.t);
-    if (want_norm) {
-        qs_status st = ensure_partials(s, ntiles);
-        if (st != QS_OK) return st;
-    }
     // persistent grid: as many workgroups as fit on the device at once, each
     // walking tiles blockIdx.x, blockIdx.x + grid, ... with the next tile's
     // loads in flight while the current one is processed
@@ -573,6 +575,11 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
                                        : reinterpret_cast<const void *>(pick_tile_kernel<double>(wide, ps.t, cl));
     const uint64_t resident = resident_groups(fn, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
+    if (want_norm) {
+        qs_status st = ensure_partials(s, grid.x);
+        if (st != QS_OK) return st;
+    }
+    if (nparts) *nparts = grid.x;
     const double S = std::ldexp((double)amp, s.n);
     double flops = 0;
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b)
