@@ -187,36 +187,77 @@ def learned_mode(a):
     from paper_2509_04955_amd import costmodel as CM
     from paper_2509_04955_amd import qsim as Q
 
+    def progress(msg):
+        print(f"[learned] {msg}", file=sys.stderr, flush=True)
+
     n = a.n
+    c = qsynth.random_u3_cnot(n, 30, seed=5)
+    gl = Q.GateList(c)
+    # the greedy reference gets its best fixed configuration, autotuned on the
+    # circuit's first 400 gates; the cost model is trained and the learned
+    # partition works inside the same tile shape
+    t0 = time.perf_counter()
+    best = Q.qs_autotune(n, Q.QS_C64, Q.GateList(c.prefix(400)), Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
+    tune_s = time.perf_counter() - t0
+    kw = dict(k_max=best.k_max, tile_qubits=best.tile_qubits, low_qubits=best.low_qubits)
+    progress(f"autotuned greedy: k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits} ({tune_s:.0f} s)")
     train = []
     for nt in sorted({min(n, 26), min(n, 28)}):
         train += [qsynth.random_u3_cnot(nt, 6, seed=31), qsynth.ucc(nt, 30, seed=32)[0],
                   qsynth.brickwork(nt, 6, seed=33), qsynth.hea(nt, 3, seed=(34, 0))]
     t0 = time.perf_counter()
-    X, y, us = CM.collect(train, widths=(1, 2, 3, 4, 5, 6), tiles=(12, 13), reps=3, max_passes=24)
+    parts = []
+    for i, tc in enumerate(train):
+        parts.append(CM.collect([tc], widths=(1, 2, 3, 4, 5, 6), tiles=(best.tile_qubits,),
+                                lows=tuple(sorted({best.low_qubits, 6})), reps=3, max_passes=24))
+        progress(f"timed passes of training circuit {i + 1}/{len(train)} ({tc.n} qubits)")
+    X = np.concatenate([p[0] for p in parts])
+    y = np.concatenate([p[1] for p in parts])
     collect_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     loss = CM.train(X, y, epochs=300, batch=64, lr=3e-3, seed=1)
     train_s = time.perf_counter() - t0
     corr = float(np.corrcoef(CM.predict(X), y)[0, 1])
-    c = qsynth.random_u3_cnot(n, 30, seed=5)
-    gl = Q.GateList(c)
-    # the greedy reference gets its best fixed configuration (autotuned);
-    # the learned partition works inside the same tile shape
-    t0 = time.perf_counter()
-    best = Q.qs_autotune(n, Q.QS_C64, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
-    tune_s = time.perf_counter() - t0
-    kw = dict(k_max=best.k_max, tile_qubits=best.tile_qubits, low_qubits=best.low_qubits)
+    progress(f"trained on {len(y)} passes: loss {loss:.4f}, corr {corr:.3f}")
     t0 = time.perf_counter()
     greedy = Q.qs_contract(n, gl, Q.opts(**kw))
     tg_plan = time.perf_counter() - t0
     t0 = time.perf_counter()
     learned = Q.qs_contract(n, gl, Q.opts(strategy=Q.STRATEGY_LEARNED, **kw))
     tl_plan = time.perf_counter() - t0
+    # the library's default fixed-width greedy plan in the same tile shape
+    kw5 = dict(kw, k_max=5)
+    greedy5 = Q.qs_contract(n, gl, Q.opts(**kw5))
+    learned5 = Q.qs_contract(n, gl, Q.opts(strategy=Q.STRATEGY_LEARNED, **kw5))
     ig, il = Q.qs_plan_info_get(greedy), Q.qs_plan_info_get(learned)
+    progress(f"plans: greedy {ig.n_passes} passes, learned {il.n_passes} passes")
     st = Q.State(n, Q.QS_C64)
+    ms_g5 = _timed(lambda: (st.set_basis(0), st.apply_plan(greedy5)))
+    ms_l5 = _timed(lambda: (st.set_basis(0), st.apply_plan(learned5)))
+    progress(f"k_max 5: greedy {ms_g5:.1f} ms, learned {ms_l5:.1f} ms")
     ms_g = _timed(lambda: (st.set_basis(0), st.apply_plan(greedy)))
+    progress(f"greedy {ms_g:.1f} ms")
     ms_l = _timed(lambda: (st.set_basis(0), st.apply_plan(learned)))
+    progress(f"learned {ms_l:.1f} ms")
+    # same state from both schedules: fidelity over all amplitudes, streamed
+    # to the host in chunks of 2^26 (two device states, bounded host memory)
+    st.set_basis(0)
+    st.apply_plan(greedy)
+    st2 = Q.State(n, Q.QS_C64)
+    st2.set_basis(0)
+    st2.apply_plan(learned)
+    torch.cuda.synchronize()
+    chunk = 1 << min(n, 26)
+    dot, ng2, nl2 = 0j, 0.0, 0.0
+    for off in range(0, 1 << n, chunk):
+        ag = Q.qs_state_copy_out(st.handle, off, chunk)
+        al = Q.qs_state_copy_out(st2.handle, off, chunk)
+        dot += np.vdot(ag, al)
+        ng2 += float(np.vdot(ag, ag).real)
+        nl2 += float(np.vdot(al, al).real)
+    fid = float(abs(dot) ** 2 / (ng2 * nl2))
+    st2.close()
+    progress(f"fidelity learned vs greedy {fid:.9f}")
     out = {"mode": "learned", "n": n, "gates": len(c), "greedy_config": kw, "autotune_s": round(tune_s, 1),
            "train_rows": int(len(y)), "train_loss": loss,
            "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
@@ -224,7 +265,10 @@ def learned_mode(a):
                       "plan_s": round(tg_plan, 2)},
            "learned": {"passes": int(il.n_passes), "blocks": int(il.n_blocks), "ms": round(ms_l, 2),
                        "plan_s": round(tl_plan, 2)},
-           "gain": round(ms_g / ms_l, 3)}
+           "gain": round(ms_g / ms_l, 3), "fidelity_learned_vs_greedy": fid,
+           "k_max5": {"greedy_ms": round(ms_g5, 2), "learned_ms": round(ms_l5, 2), "gain": round(ms_g5 / ms_l5, 3)}}
+    Q.qs_plan_destroy(greedy5)
+    Q.qs_plan_destroy(learned5)
     st.close()
     Q.qs_plan_destroy(greedy)
     Q.qs_plan_destroy(learned)

@@ -12,6 +12,7 @@ to pick the width per window.  All numerics run in libqsim.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import math
 
 import numpy as np
@@ -35,28 +36,28 @@ def time_passes(plan, dtype: int, reps: int = 3) -> np.ndarray:
 
 
 def collect(circuits, dtype: int = Q.QS_C64, widths=(1, 2, 3, 4, 5, 6), tiles=(12, 13), reps: int = 3,
-            max_passes: int = 64):
-    """Timing dataset over circuits x widths x tiles (the first `max_passes`
-    passes of each plan are timed).  Returns (X, target, us)."""
+            max_passes: int = 64, lows=(0,)):
+    """Timing dataset over circuits x widths x tiles x fixed-low-qubit counts
+    (0 = the library default; the first `max_passes` passes of each plan are
+    timed).  Returns (X, target, us)."""
     xs, ys = [], []
     for c in circuits:
         gl = Q.GateList(c)
-        for t in tiles:
-            for k in widths:
-                if dtype == Q.QS_C128 and k > 5:
-                    continue
-                try:
-                    plan = Q.qs_contract(c.n, gl, Q.opts(k_max=k, tile_qubits=t, dtype=dtype))
-                except Q.QsimError:
-                    continue
-                try:
-                    feats = pass_features(plan)[:max_passes]
-                    # time a plan restricted to its first passes: prefix circuit
-                    us = time_passes(plan, dtype, reps)[: len(feats)]
-                finally:
-                    Q.qs_plan_destroy(plan)
-                xs.append(feats)
-                ys.append(us)
+        for t, low, k in itertools.product(tiles, lows, widths):
+            if dtype == Q.QS_C128 and k > 5:
+                continue
+            try:
+                plan = Q.qs_contract(c.n, gl, Q.opts(k_max=k, tile_qubits=t, low_qubits=low, dtype=dtype))
+            except Q.QsimError:
+                continue
+            try:
+                feats = pass_features(plan)[:max_passes]
+                # time a plan restricted to its first passes: prefix circuit
+                us = time_passes(plan, dtype, reps)[: len(feats)]
+            finally:
+                Q.qs_plan_destroy(plan)
+            xs.append(feats)
+            ys.append(us)
     X = np.concatenate(xs).astype(np.float32)
     us = np.concatenate(ys)
     return X, target(us, X), us

@@ -364,6 +364,23 @@ void swizzle_mfma(const std::vector<cd> &U, int k, bool lds_layout, std::vector<
             }
 }
 
+// Host-side operands of mfma3m_block_lds: A_g for g = Ur, Ui, Ur + Ui, entry
+// A_g[16 m + l % 16][4 s + l / 16] for M-tile m, step s, lane l, stored as
+// [g][m][s / 4][l][s % 4].
+void swizzle_mfma3m(const std::vector<cd> &U, int k, std::vector<float> &out) {
+    const int D = 1 << k, MT = D / 16, S = D / 4, S4 = S / 4;
+    const size_t o0 = out.size();
+    out.resize(o0 + (size_t)3 * MT * S * 64);
+    for (int g = 0; g < 3; ++g)
+        for (int m = 0; m < MT; ++m)
+            for (int s = 0; s < S; ++s)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const cd u = U[(size_t)(16 * m + lane % 16) * D + (4 * s + lane / 16)];
+                    const double v = g == 0 ? u.real() : g == 1 ? u.imag() : u.real() + u.imag();
+                    out[o0 + ((((size_t)g * MT + m) * S4 + s / 4) * 64 + lane) * 4 + s % 4] = (float)v;
+                }
+}
+
 // Structure of a block matrix: monomial (exactly one entry per column with
 // |u| > kZeroTol, entries below it being rounding residue of exact zeros of
 // the gate product) or dense.
@@ -422,7 +439,8 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
         d.kind = BK_MFMA;
         d.mat_off = (int32_t)pool.size();
         std::vector<float> a;
-        swizzle_mfma(blk.U, d.k, lds, a);
+        if (lds && d.k >= 4) swizzle_mfma3m(blk.U, d.k, a);
+        else swizzle_mfma(blk.U, d.k, lds, a);
         for (float v : a) pool.push_back((R)v);
     } else {
         d.kind = BK_DENSE;
@@ -443,7 +461,9 @@ size_t pass_operand_bytes(const qs_plan_s &p, const HPass &ps, qs_dtype dt) {
         const HBlock &blk = p.blocks[i];
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
-        size_t e = kind == BK_MONO ? 4 * (size_t)D : kind == BK_MFMA ? (size_t)4 * D * D : 2 * (size_t)D * D;
+        size_t e = kind == BK_MONO   ? 4 * (size_t)D
+                   : kind == BK_MFMA ? (k >= 4 ? (size_t)3 * D * D : (size_t)4 * D * D)
+                                     : 2 * (size_t)D * D;
         e = (e + 3) / 4 * 4;
         b += e * (dt == QS_C64 ? 4 : 8);
     }

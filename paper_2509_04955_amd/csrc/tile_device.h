@@ -403,12 +403,124 @@ __device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockD
     }
 }
 
+// ---- complex GEMM with three real products (complex64, K = 4, 5) ------------
+// For staged passes the 2^K x 2^K complex block U = Ur + i Ui is applied with
+// Gauss's three-multiplication form: T1 = Ur Xr, T2 = Ui Xi,
+// T3 = (Ur + Ui)(Xr + Xi); Re Y = T1 - T2, Im Y = T3 - T1 - T2.  That is three
+// real 2^K x 2^K GEMMs (3 * 4^K multiply-adds per column) instead of the
+// 2^(K+1)-square real embedding (4 * 4^K).  v_mfma_f32_16x16x4f32, step s
+// covers K indices 4s..4s+3: lane l supplies A_g[16m + l%16][4s + l/16] and
+// X[4s + l/16][column l%16], and holds output rows 16m + 4(l/16) + q of all
+// three products, so it writes complete amplitudes (re, im).  Operand layout
+// in LDS: [g = Ur, Ui, Ur+Ui][M-tile][s/4][lane][s%4].  As in mfma_block_lds
+// each wave owns whole chunks: no barrier inside the block.  K = 4 keeps all
+// of A in registers for the block; K = 5 re-reads it per chunk.
+template <int K>
+__device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const BlockDev *bd, const float *As) {
+    static_assert(K == 4 || K == 5, "three-product GEMM needs 2^K >= 16");
+    constexpr int D = 1 << K;
+    constexpr int MT = D / 16;
+    constexpr int S = D / 4;
+    constexpr int S4 = S / 4;
+    constexpr int CPI = K >= 5 ? 1 : 2;
+    constexpr bool HOIST = K == 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gq = lane >> 4, jc = lane & 15;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    auto deposit = [&](int r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if ((r >> j) & 1) o |= 1u << pos[j];
+        return o;
+    };
+    uint32_t offB[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) offB[s] = sw(deposit(4 * s + gq));
+    uint32_t oc[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) oc[m][q] = sw(deposit(16 * m + 4 * gq + q));
+    const floatx4 *A4 = reinterpret_cast<const floatx4 *>(As);
+    auto aidx = [&](int g, int m, int s4) { return ((g * MT + m) * S4 + s4) * 64 + lane; };
+    floatx4 ah[HOIST ? 3 * MT * S4 : 1];
+    if constexpr (HOIST) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int s4 = 0; s4 < S4; ++s4) ah[(g * MT + m) * S4 + s4] = A4[aidx(g, m, s4)];
+    }
+    const uint32_t nchunks = (1u << (T - K)) / 16;
+    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += 4 * CPI) {
+        uint32_t cb[CPI];
+        float2 bv[CPI][S];
+#pragma unroll
+        for (int h = 0; h < CPI; ++h) {
+            const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
+            uint32_t c = ch * 16 + jc;
+#pragma unroll
+            for (int j = 0; j < K; ++j) c = ins0_32(c, pos[j]);
+            cb[h] = sw(c);
+#pragma unroll
+            for (int s = 0; s < S; ++s) bv[h][s] = tile[cb[h] ^ offB[s]];
+        }
+        floatx4 acc[CPI][3][MT];
+#pragma unroll
+        for (int h = 0; h < CPI; ++h)
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) acc[h][g][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s4 = 0; s4 < S4; ++s4) {
+            floatx4 a[3][MT];
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) a[g][m] = HOIST ? ah[(g * MT + m) * S4 + s4] : A4[aidx(g, m, s4)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int s = 4 * s4 + u;
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int h = 0; h < CPI; ++h) {
+                        const float xr = bv[h][s].x, xi = bv[h][s].y;
+                        acc[h][0][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][m][u], xr, acc[h][0][m], 0, 0, 0);
+                        acc[h][1][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][m][u], xi, acc[h][1][m], 0, 0, 0);
+                        acc[h][2][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2][m][u], xr + xi, acc[h][2][m], 0, 0,
+                                                                            0);
+                    }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < CPI; ++h) {
+            if (ch0 + h < nchunks) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float t1 = acc[h][0][m][q], t2 = acc[h][1][m][q], t3 = acc[h][2][m][q];
+                        tile[cb[h] ^ oc[m][q]] = make_float2(t1 - t2, t3 - t1 - t2);
+                    }
+            }
+        }
+    }
+}
+
 // ---- the pass kernel ------------------------------------------------------
 // WIDE = false keeps register use low (dense VALU blocks up to k = 3, complex64
 // dense k = 4, 5 through MFMA, monomial blocks of any width); WIDE = true adds
 // dense VALU blocks with k >= 4.  The host picks the variant per pass.
 // CL = true: the pass's block operands were staged in LDS at `cst` (pool
-// element cl_off is cst[0]); complex64 MFMA blocks (k = 3, 4, 5) and monomial
+// element cl_off is cst[0]); complex64 MFMA blocks (k = 3 embedded, k = 4, 5
+// three-product form) and monomial
 // blocks with k >= 4 (per-lane records) read them there, dense VALU blocks and
 // narrow monomial blocks keep their wave-uniform scalar loads from the pool.
 template <typename R, bool WIDE, bool CL = false>
@@ -423,8 +535,8 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
             if constexpr (CL) {
                 const float *As = cst + (bd->mat_off - cl_off);
                 if (k == 3) mfma_block_lds<3>(tile, T, bd, As);
-                else if (k == 4) mfma_block_lds<4>(tile, T, bd, As);
-                else mfma_block_lds<5>(tile, T, bd, As);
+                else if (k == 4) mfma3m_block_lds<4>(tile, T, bd, As);
+                else mfma3m_block_lds<5>(tile, T, bd, As);
             } else {
                 if (k == 4) mfma_block<4>(tile, T, bd, U);
                 else mfma_block<5>(tile, T, bd, U);
