@@ -277,7 +277,8 @@ def learned_mode(a):
 
 def brickwork_mode(a):
     """28-qubit brickwork (Haar U3 on every qubit + alternating CNOT pairs,
-    depth 40): complex64 and complex128, gate-by-gate vs fused (k_max 5)."""
+    depth 40): complex64 and complex128, gate-by-gate vs fused (k_max 5 or
+    below, tile shape autotuned per dtype)."""
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
@@ -286,15 +287,19 @@ def brickwork_mode(a):
     gl = Q.GateList(c)
     out = {"mode": "brickwork", "n": n, "gates": len(c)}
     for dt, name in ((Q.QS_C64, "c64"), (Q.QS_C128, "c128")):
+        best = Q.qs_autotune(n, dt, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
+        print(f"[brickwork] {name}: autotuned k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits}",
+              file=sys.stderr, flush=True)
         st = Q.State(n, dt)
-        kmax = 5
-        plan = Q.qs_contract(n, gl, Q.opts(k_max=kmax, dtype=dt))
+        plan = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
+                                           low_qubits=best.low_qubits, dtype=dt))
         info = Q.qs_plan_info_get(plan)
         ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
         ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
         S = (8 if dt == Q.QS_C64 else 16) * (1 << n)
         out[name] = {"plain_ms": round(ms_plain, 2), "fused_ms": round(ms_fused, 2),
                      "speedup": round(ms_plain / ms_fused, 2), "passes": int(info.n_passes),
+                     "k_max": best.k_max, "tile_qubits": best.tile_qubits, "low_qubits": best.low_qubits,
                      "plain_effective_gbs": round(plain_bytes(c, S) / (ms_plain * 1e-3) / 1e9, 1),
                      "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1),
                      "fused_streamed_gbs": round((info.n_passes * 2 + 1) * S / (ms_fused * 1e-3) / 1e9, 1)}
@@ -309,17 +314,20 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               "(the multi-GPU path is not part of this build)", file=sys.stderr)
         sys.exit(2)
+    import torch
+
+    # torch owns the device context; initialise it before any library call
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    torch.cuda.init()
     if a.mode != "ucc":
         {"copy": copy_mode, "batch": batch_mode, "learned": learned_mode, "brickwork": brickwork_mode}[a.mode](a)
         return
     import numpy as np
-    import torch
 
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    torch.cuda.set_device(0)
     n = a.n
     circ, rots = qsynth.ucc(n, n_exp=a.n_exp, seed=a.seed)
     gl = Q.GateList(circ)

@@ -42,15 +42,27 @@ using namespace tiledev;
 constexpr int kPrefetch = 6;
 
 // Streaming accesses to the state bypass cache retention (non-temporal): each
-// amplitude is read once and written once per pass.
-typedef float nt4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ld_nt(const float4 *p) {
-    const nt4 v = __builtin_nontemporal_load(reinterpret_cast<const nt4 *>(p));
-    return make_float4(v.x, v.y, v.z, v.w);
+// amplitude is read once and written once per pass.  A thread moves 16-byte
+// vectors: two complex64 amplitudes (4 floats) or one complex128 (2 doubles).
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+template <typename R>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using V = vf4;
+};
+template <>
+struct Vec16<double> {
+    using V = vd2;
+};
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V *p) {
+    return __builtin_nontemporal_load(p);
 }
-__device__ __forceinline__ void st_nt(float4 *p, float4 v) {
-    const nt4 w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<nt4 *>(p));
+template <typename V>
+__device__ __forceinline__ void st_nt(V *p, V v) {
+    __builtin_nontemporal_store(v, p);
 }
 
 // Tile index li of 16-byte vector vi = tid + TT*j splits into a per-thread
@@ -74,7 +86,8 @@ __device__ __forceinline__ void st_nt(float4 *p, float4 v) {
 // workgroup for the operands.
 template <typename R, bool WIDE, int NJ, bool CL>
 constexpr int tile_waves() {
-    return WIDE ? 1 : (sizeof(R) == 4 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
+    // NJ = 0 (tiles below 2^9 complex64 amplitudes) never fills a CU anyway
+    return WIDE ? 1 : (sizeof(R) == 4 && NJ > 0 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
 }
 
 template <typename R, bool WIDE, int NJ, bool CL>
@@ -84,7 +97,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
-    constexpr int PFMAX = tile_waves<R, WIDE, NJ, CL>() <= 3 ? 16 : kPrefetch;
+    constexpr int PFMAX = tile_waves<R, WIDE, NJ, CL>() <= 3 ? (sizeof(R) == 8 ? 8 : 16) : kPrefetch;
     constexpr int PF = NJ > 0 ? (NJ < PFMAX ? NJ : PFMAX) : kPrefetch;
     constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -98,24 +111,14 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
     const uint64_t g_t = active ? tile_offset(my_li, pa) : 0;
     const uint32_t s_t = sw(my_li);
     const uint32_t nj = NJ > 0 ? (uint32_t)NJ : (tsize + TT * APV - 1) / (TT * APV);   // vectors per thread
-    float4 pre[PF];
-    auto gaddr = [&](uint64_t base, uint32_t j) -> const float4 * {
-        return reinterpret_cast<const float4 *>(psi + (base | g_t | tile_offset(j * TT * APV, pa)));
+    using V = typename Vec16<R>::V;
+    V pre[PF];
+    auto gaddr = [&](uint64_t base, uint32_t j) -> V * {
+        return reinterpret_cast<V *>(psi + (base | g_t | tile_offset(j * TT * APV, pa)));
     };
-    auto lds_put = [&](uint32_t j, float4 v) {
+    auto lds_put = [&](uint32_t j, V v) {
         const uint32_t si = s_t ^ sw(j * TT * APV);
-        if constexpr (F32) {
-            v.x *= sc;
-            v.y *= sc;
-            v.z *= sc;
-            v.w *= sc;
-            *reinterpret_cast<float4 *>(tile + si) = v;
-        } else {
-            double2 d = __builtin_bit_cast(double2, v);
-            d.x *= sc;
-            d.y *= sc;
-            tile[si] = d;
-        }
+        *reinterpret_cast<V *>(tile + si) = v * sc;
     };
     // Vectors of a generic tile beyond the prefetch depth: loaded in batches
     // through the prefetch registers once those are in LDS.
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
     if constexpr (CL) {
         constexpr int EPV = 16 / sizeof(R);
         for (int i = threadIdx.x * EPV; i < pa.cl_len; i += TT * EPV)
-            *reinterpret_cast<float4 *>(cst + i) = *reinterpret_cast<const float4 *>(pool + pa.cl_off + i);
+            *reinterpret_cast<V *>(cst + i) = *reinterpret_cast<const V *>(pool + pa.cl_off + i);
     }
     uint64_t base = tile_base(tileid, pa);
     if (active) {
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
         for (int j = 0; j < PF; ++j)
             if ((uint32_t)j < nj) pre[j] = ld_nt(gaddr(base, j));
         if constexpr (EX > 0) {
-            float4 ex[EX];
+            V ex[EX];
 #pragma unroll
             for (int i = 0; i < EX; ++i) ex[i] = ld_nt(gaddr(base, PF + i));
 #pragma unroll
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
             apply_block<R, WIDE, CL>(tile, T, blocks + pa.block0 + b, pool, cst, pa.cl_off);
             __syncthreads();
         }
-        float4 ex[EX > 0 ? EX : 1];
+        V ex[EX > 0 ? EX : 1];
         if constexpr (EX > 0) {
 #pragma unroll
             for (int i = 0; i < EX; ++i) ex[i] = ld_nt(gaddr(nbase, PF + i));
@@ -192,16 +195,12 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
         double nacc = 0.0;
         if (active) {
             for (uint32_t j = 0; j < nj; ++j) {
-                // keep the scheduler from hoisting every LDS read of the
-                // store phase ahead of the stores (register pressure)
-                if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
-                const float4 v = *reinterpret_cast<const float4 *>(tile + (s_t ^ sw(j * TT * APV)));
-                st_nt(const_cast<float4 *>(gaddr(base, j)), v);
+                const V v = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * TT * APV)));
+                st_nt(gaddr(base, j), v);
                 if constexpr (F32) {
                     nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
                 } else {
-                    const double2 d = __builtin_bit_cast(double2, v);
-                    nacc += d.x * d.x + d.y * d.y;
+                    nacc += v.x * v.x + v.y * v.y;
                 }
             }
         }
@@ -285,9 +284,12 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl) {
     const int vpt = (1 << t) / (TT * APV);   // 16-byte vectors per thread
     if (wide) return k_tile_pass<R, true, 0, false>;
     if ((1 << t) == vpt * TT * APV) {
-        if constexpr (sizeof(R) == 4) {
-            if (cl) {
+        if (cl) {
+            if constexpr (sizeof(R) == 4) {
                 if (vpt == 4) return k_tile_pass<R, false, 4, true>;
+                if (vpt == 8) return k_tile_pass<R, false, 8, true>;
+                if (vpt == 16) return k_tile_pass<R, false, 16, true>;
+            } else {
                 if (vpt == 8) return k_tile_pass<R, false, 8, true>;
                 if (vpt == 16) return k_tile_pass<R, false, 16, true>;
             }
@@ -302,15 +304,17 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl) {
 }
 
 // LDS bytes a pass may use for staged operands: what is left of the CU's LDS
-// share per workgroup at the occupancy the staged variant targets (2^11: 4,
-// 2^12: 3, 2^13: 2 workgroups per CU), minus the tile and a margin for the
-// kernel's static LDS.  0 = no staged variant for this tile.
+// share per workgroup at the occupancy the staged variant targets (complex64
+// 2^11: 4, 2^12: 3, 2^13: 2 workgroups per CU; complex128 2^11, 2^12: 2),
+// minus the tile and a margin for the kernel's static LDS.  0 = no staged
+// variant for this tile.
 size_t lds_operand_budget(int t, qs_dtype dt) {
-    if (dt != QS_C64) return 0;
     constexpr size_t kLds = 160 * 1024, kMargin = 512;
-    const int wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : 0;
+    int wgs = 0;
+    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : 0;
+    else wgs = t == 11 || t == 12 ? 2 : 0;   // complex128 variants run 2 workgroups per CU
     if (!wgs) return 0;
-    const size_t share = (kLds / wgs) & ~(size_t)1023, tile = (size_t)8 << t;
+    const size_t share = (kLds / wgs) & ~(size_t)1023, tile = (size_t)(dt == QS_C64 ? 8 : 16) << t;
     return share > tile + kMargin ? share - tile - kMargin : 0;
 }
 
@@ -343,7 +347,8 @@ bool mfma_enabled() {
 // R = 16 mt + l % 16 and input (row 4 (s / 2) + l / 16, part s % 2).
 // Layout [mt][s][lane] for mfma_block, [mt][s / 4][lane][s % 4] for
 // mfma_block_lds (16-byte LDS reads).
-void swizzle_mfma(const std::vector<cd> &U, int k, bool lds_layout, std::vector<float> &out) {
+template <typename R>
+void swizzle_mfma(const std::vector<cd> &U, int k, bool lds_layout, std::vector<R> &out) {
     const int D = 1 << k, MT = 2 * D / 16, S = 2 * D / 4;
     const size_t o0 = out.size();
     out.resize(o0 + (size_t)MT * S * 64);
@@ -351,23 +356,24 @@ void swizzle_mfma(const std::vector<cd> &U, int k, bool lds_layout, std::vector<
         for (int s = 0; s < S; ++s)
             for (int lane = 0; lane < 64; ++lane) {
                 const int i = lane % 16, g = lane / 16;
-                const int R = 16 * mt + i;
+                const int row = 16 * mt + i;
                 const int r = 4 * (s / 2) + g, p = s % 2;
-                const int rr = R % D, ro = R / D;
+                const int rr = row % D, ro = row / D;
                 const cd u = U[(size_t)rr * D + r];
                 double v;
                 if (ro == 0) v = p == 0 ? u.real() : -u.imag();
                 else v = p == 0 ? u.imag() : u.real();
                 const size_t idx = lds_layout ? (((size_t)mt * (S / 4) + s / 4) * 64 + lane) * 4 + s % 4
                                               : ((size_t)mt * S + s) * 64 + lane;
-                out[o0 + idx] = (float)v;
+                out[o0 + idx] = (R)v;
             }
 }
 
 // Host-side operands of mfma3m_block_lds: A_g for g = Ur, Ui, Ur + Ui, entry
 // A_g[16 m + l % 16][4 s + l / 16] for M-tile m, step s, lane l, stored as
 // [g][m][s / 4][l][s % 4].
-void swizzle_mfma3m(const std::vector<cd> &U, int k, std::vector<float> &out) {
+template <typename R>
+void swizzle_mfma3m(const std::vector<cd> &U, int k, std::vector<R> &out) {
     const int D = 1 << k, MT = D / 16, S = D / 4, S4 = S / 4;
     const size_t o0 = out.size();
     out.resize(o0 + (size_t)3 * MT * S * 64);
@@ -377,7 +383,7 @@ void swizzle_mfma3m(const std::vector<cd> &U, int k, std::vector<float> &out) {
                 for (int lane = 0; lane < 64; ++lane) {
                     const cd u = U[(size_t)(16 * m + lane % 16) * D + (4 * s + lane / 16)];
                     const double v = g == 0 ? u.real() : g == 1 ? u.imag() : u.real() + u.imag();
-                    out[o0 + ((((size_t)g * MT + m) * S4 + s / 4) * 64 + lane) * 4 + s % 4] = (float)v;
+                    out[o0 + ((((size_t)g * MT + m) * S4 + s / 4) * 64 + lane) * 4 + s % 4] = (R)v;
                 }
 }
 
@@ -438,10 +444,8 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
     } else if (kind == BK_MFMA) {
         d.kind = BK_MFMA;
         d.mat_off = (int32_t)pool.size();
-        std::vector<float> a;
-        if (lds && d.k >= 4) swizzle_mfma3m(blk.U, d.k, a);
-        else swizzle_mfma(blk.U, d.k, lds, a);
-        for (float v : a) pool.push_back((R)v);
+        if (lds && d.k >= 4) swizzle_mfma3m<R>(blk.U, d.k, pool);
+        else swizzle_mfma<R>(blk.U, d.k, lds, pool);
     } else {
         d.kind = BK_DENSE;
         d.mat_off = (int32_t)pool.size();
@@ -493,7 +497,12 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     const int k = (int)b.qubits.size();
     std::vector<int> tmp;
     if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp)) return BK_MONO;
-    if (dt == QS_C64 && (k == 4 || k == 5 || (lds && k == 3)) && t - k >= 4 && mfma_enabled()) return BK_MFMA;
+    // complex64: MFMA for k = 4, 5 (k = 3 too when staged); complex128: FP64
+    // MFMA only in staged passes (the unstaged FP64 path is the vector ALU)
+    if (t - k >= 4 && mfma_enabled()) {
+        if (dt == QS_C64 && (k == 4 || k == 5 || (lds && k == 3))) return BK_MFMA;
+        if (dt == QS_C128 && lds && k >= 3 && k <= 5) return BK_MFMA;
+    }
     return BK_DENSE;
 }
 

@@ -15,6 +15,7 @@
 #include "internal.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 namespace qs {
 namespace tiledev {
@@ -59,6 +60,29 @@ struct AmpOf<float> {
 template <>
 struct AmpOf<double> {
     using A = double2;
+};
+
+// 16x16x4 MFMA per real type: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// for both types; output item q of lane l is column l%16 and row
+// row(l/16, q): 4(l/16) + q for v_mfma_f32_16x16x4f32, (l/16) + 4q for
+// v_mfma_f64_16x16x4f64 (measured on gfx950 with a lane-layout probe).
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    using V4 = floatx4;
+    __device__ __forceinline__ static V4 op(float a, float b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __host__ __device__ static constexpr int row(int g, int q) { return 4 * g + q; }
+};
+template <>
+struct Mfma<double> {
+    using V4 = doublex4;
+    __device__ __forceinline__ static V4 op(double a, double b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __host__ __device__ static constexpr int row(int g, int q) { return g + 4 * q; }
 };
 
 // LDS layout: amplitude li of the tile lives at sw(li) = li ^ (((li >> 4) & 7) << 1).
@@ -319,10 +343,12 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
 // any of its outputs is written and no other wave touches the chunk, so the
 // block needs no barrier of its own.  Output row R = 16 m + 4 (lane/16) + q is
 // amplitude R mod 2^K, real part when R < 2^K (K = 3 has one M-tile holding
-// both parts).  CPI chunks are in flight per wave (CPI * MT accumulator
+// both parts); for FP64 the row of item q is 16 m + lane/16 + 4q.  CPI chunks are in flight per wave (CPI * MT accumulator
 // chains).
-template <int K>
-__device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockDev *bd, const float *As) {
+template <int K, typename R>
+__device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T, const BlockDev *bd, const R *As) {
+    using A = typename AmpOf<R>::A;
+    using V4 = typename Mfma<R>::V4;
     constexpr int D = 1 << K;
     constexpr int MT = 2 * D / 16;
     constexpr int S = 2 * D / 4;
@@ -351,15 +377,15 @@ __device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockD
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int R = 16 * m + 4 * gq + q;
-            oc[m][q] = (2u * sw(deposit(R % D))) | (uint32_t)(R / D);
+            const int row = 16 * m + Mfma<R>::row(gq, q);
+            oc[m][q] = (2u * sw(deposit(row % D))) | (uint32_t)(row / D);
         }
-    float *tf = reinterpret_cast<float *>(tile);
-    const floatx4 *A4 = reinterpret_cast<const floatx4 *>(As);
+    R *tf = reinterpret_cast<R *>(tile);
+    const V4 *A4 = reinterpret_cast<const V4 *>(As);
     const uint32_t nchunks = (1u << (T - K)) / 16;
     for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += 4 * CPI) {
         uint32_t cb[CPI];
-        float2 bv[CPI][NB];
+        A bv[CPI][NB];
 #pragma unroll
         for (int h = 0; h < CPI; ++h) {
             const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
@@ -370,14 +396,14 @@ __device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockD
 #pragma unroll
             for (int m = 0; m < NB; ++m) bv[h][m] = tile[cb[h] ^ offB[m]];
         }
-        floatx4 acc[CPI][MT];
+        V4 acc[CPI][MT];
 #pragma unroll
         for (int h = 0; h < CPI; ++h)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) acc[h][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int m = 0; m < MT; ++m) acc[h][m] = V4{0, 0, 0, 0};
 #pragma unroll
         for (int s4 = 0; s4 < S / 4; ++s4) {
-            floatx4 a[MT];
+            V4 a[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m) a[m] = A4[(m * (S / 4) + s4) * 64 + lane];
 #pragma unroll
@@ -387,8 +413,7 @@ __device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockD
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int h = 0; h < CPI; ++h)
-                        acc[h][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            a[m][u], (s & 1) ? bv[h][s >> 1].y : bv[h][s >> 1].x, acc[h][m], 0, 0, 0);
+                        acc[h][m] = Mfma<R>::op(a[m][u], (s & 1) ? bv[h][s >> 1].y : bv[h][s >> 1].x, acc[h][m]);
             }
         }
 #pragma unroll
@@ -410,13 +435,15 @@ __device__ __forceinline__ void mfma_block_lds(float2 *tile, int T, const BlockD
 // real 2^K x 2^K GEMMs (3 * 4^K multiply-adds per column) instead of the
 // 2^(K+1)-square real embedding (4 * 4^K).  v_mfma_f32_16x16x4f32, step s
 // covers K indices 4s..4s+3: lane l supplies A_g[16m + l%16][4s + l/16] and
-// X[4s + l/16][column l%16], and holds output rows 16m + 4(l/16) + q of all
+// X[4s + l/16][column l%16], and holds output rows 16m + Mfma::row(l/16, q) of all
 // three products, so it writes complete amplitudes (re, im).  Operand layout
 // in LDS: [g = Ur, Ui, Ur+Ui][M-tile][s/4][lane][s%4].  As in mfma_block_lds
 // each wave owns whole chunks: no barrier inside the block.  K = 4 keeps all
 // of A in registers for the block; K = 5 re-reads it per chunk.
-template <int K>
-__device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const BlockDev *bd, const float *As) {
+template <int K, typename R>
+__device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int T, const BlockDev *bd, const R *As) {
+    using A = typename AmpOf<R>::A;
+    using V4 = typename Mfma<R>::V4;
     static_assert(K == 4 || K == 5, "three-product GEMM needs 2^K >= 16");
     constexpr int D = 1 << K;
     constexpr int MT = D / 16;
@@ -444,10 +471,10 @@ __device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const Bloc
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) oc[m][q] = sw(deposit(16 * m + 4 * gq + q));
-    const floatx4 *A4 = reinterpret_cast<const floatx4 *>(As);
+        for (int q = 0; q < 4; ++q) oc[m][q] = sw(deposit(16 * m + Mfma<R>::row(gq, q)));
+    const V4 *A4 = reinterpret_cast<const V4 *>(As);
     auto aidx = [&](int g, int m, int s4) { return ((g * MT + m) * S4 + s4) * 64 + lane; };
-    floatx4 ah[HOIST ? 3 * MT * S4 : 1];
+    V4 ah[HOIST ? 3 * MT * S4 : 1];
     if constexpr (HOIST) {
 #pragma unroll
         for (int g = 0; g < 3; ++g)
@@ -459,7 +486,7 @@ __device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const Bloc
     const uint32_t nchunks = (1u << (T - K)) / 16;
     for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += 4 * CPI) {
         uint32_t cb[CPI];
-        float2 bv[CPI][S];
+        A bv[CPI][S];
 #pragma unroll
         for (int h = 0; h < CPI; ++h) {
             const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
@@ -470,16 +497,16 @@ __device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const Bloc
 #pragma unroll
             for (int s = 0; s < S; ++s) bv[h][s] = tile[cb[h] ^ offB[s]];
         }
-        floatx4 acc[CPI][3][MT];
+        V4 acc[CPI][3][MT];
 #pragma unroll
         for (int h = 0; h < CPI; ++h)
 #pragma unroll
             for (int g = 0; g < 3; ++g)
 #pragma unroll
-                for (int m = 0; m < MT; ++m) acc[h][g][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int m = 0; m < MT; ++m) acc[h][g][m] = V4{0, 0, 0, 0};
 #pragma unroll
         for (int s4 = 0; s4 < S4; ++s4) {
-            floatx4 a[3][MT];
+            V4 a[3][MT];
 #pragma unroll
             for (int g = 0; g < 3; ++g)
 #pragma unroll
@@ -491,11 +518,10 @@ __device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const Bloc
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int h = 0; h < CPI; ++h) {
-                        const float xr = bv[h][s].x, xi = bv[h][s].y;
-                        acc[h][0][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][m][u], xr, acc[h][0][m], 0, 0, 0);
-                        acc[h][1][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][m][u], xi, acc[h][1][m], 0, 0, 0);
-                        acc[h][2][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2][m][u], xr + xi, acc[h][2][m], 0, 0,
-                                                                            0);
+                        const R xr = bv[h][s].x, xi = bv[h][s].y;
+                        acc[h][0][m] = Mfma<R>::op(a[0][m][u], xr, acc[h][0][m]);
+                        acc[h][1][m] = Mfma<R>::op(a[1][m][u], xi, acc[h][1][m]);
+                        acc[h][2][m] = Mfma<R>::op(a[2][m][u], xr + xi, acc[h][2][m]);
                     }
             }
         }
@@ -506,8 +532,11 @@ __device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const Bloc
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float t1 = acc[h][0][m][q], t2 = acc[h][1][m][q], t3 = acc[h][2][m][q];
-                        tile[cb[h] ^ oc[m][q]] = make_float2(t1 - t2, t3 - t1 - t2);
+                        const R t1 = acc[h][0][m][q], t2 = acc[h][1][m][q], t3 = acc[h][2][m][q];
+                        A y;
+                        y.x = t1 - t2;
+                        y.y = t3 - t1 - t2;
+                        tile[cb[h] ^ oc[m][q]] = y;
                     }
             }
         }
@@ -519,8 +548,8 @@ __device__ __forceinline__ void mfma3m_block_lds(float2 *tile, int T, const Bloc
 // dense k = 4, 5 through MFMA, monomial blocks of any width); WIDE = true adds
 // dense VALU blocks with k >= 4.  The host picks the variant per pass.
 // CL = true: the pass's block operands were staged in LDS at `cst` (pool
-// element cl_off is cst[0]); complex64 MFMA blocks (k = 3 embedded, k = 4, 5
-// three-product form) and monomial
+// element cl_off is cst[0]); MFMA blocks (k = 3 embedded, k = 4, 5
+// three-product form; FP32 or FP64 matrix cores) and monomial
 // blocks with k >= 4 (per-lane records) read them there, dense VALU blocks and
 // narrow monomial blocks keep their wave-uniform scalar loads from the pool.
 template <typename R, bool WIDE, bool CL = false>
@@ -530,17 +559,16 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     const int kind = bd->kind;
     const R *U = pool + bd->mat_off;
     constexpr bool F32 = sizeof(R) == 4;
-    if constexpr (F32) {
-        if (kind == BK_MFMA) {
-            if constexpr (CL) {
-                const float *As = cst + (bd->mat_off - cl_off);
-                if (k == 3) mfma_block_lds<3>(tile, T, bd, As);
-                else if (k == 4) mfma3m_block_lds<4>(tile, T, bd, As);
-                else mfma3m_block_lds<5>(tile, T, bd, As);
-            } else {
-                if (k == 4) mfma_block<4>(tile, T, bd, U);
-                else mfma_block<5>(tile, T, bd, U);
-            }
+    if (kind == BK_MFMA) {
+        if constexpr (CL) {
+            const R *As = cst + (bd->mat_off - cl_off);
+            if (k == 3) mfma_block_lds<3, R>(tile, T, bd, As);
+            else if (k == 4) mfma3m_block_lds<4, R>(tile, T, bd, As);
+            else mfma3m_block_lds<5, R>(tile, T, bd, As);
+            return;
+        } else if constexpr (F32) {
+            if (k == 4) mfma_block<4>(tile, T, bd, U);
+            else mfma_block<5>(tile, T, bd, U);
             return;
         }
     }
