@@ -3,8 +3,11 @@
 // Each state (its own qubit count, circuit and Pauli-sum Hamiltonian) gets a
 // contraction plan; all passes of all states and all expectation work become
 // one work queue:
-//   * pass items (state s, pass p, tile i): the tile kernel's work for one tile;
-//   * energy items (state s, term group, pair chunk): Pauli expectation partials.
+//   * pass items (state s, pass p, tiles i..i+G-1): the tile kernel's work for
+//     a group of consecutive tiles (G up to 16), with the next tile's loads in
+//     registers while the current one is processed;
+//   * energy items (state s, group of 8 terms, chunk of 2^16 amplitudes):
+//     Pauli expectation partials.
 // Items are ordered pass-major across states (all first passes, then all
 // second passes, ..., then the energy items), so an item only ever waits for
 // items earlier in the queue.  The grid never exceeds the resident workgroup
@@ -37,7 +40,9 @@ constexpr int kPassItem = 0, kEnergyItem = 1;
 // wall clock, read with s_memrealtime): a wait that long means the item it
 // waits for will not arrive, and the kernel then drains with an error record.
 constexpr double kWaitSeconds = 1.0;
-constexpr uint64_t kPairsPerItem = 1ull << 16;
+// energy items: kTermsPerItem terms of one state over kAmpsPerItem amplitudes
+constexpr uint64_t kAmpsPerItem = 1ull << 16;
+constexpr int kTermsPerItem = 8;
 
 struct Seg {
     uint64_t first;   // first item index
@@ -51,6 +56,7 @@ struct Seg {
 struct PassDev {
     PassArgs pa;
     uint64_t ntiles;
+    uint64_t tiles_per_item;   // a pass item covers this many consecutive tiles
     const BlockDev *blocks;
     const void *pool;
     uint64_t need_done;      // tiles of this state completed by earlier passes
@@ -122,51 +128,104 @@ __device__ double wg_sum(const double *v, uint32_t count, double *red) {
     return t;
 }
 
+// Tiles [t0, t1) of one pass of one state: each tile is loaded into LDS,
+// every block of the pass is applied, and the tile is written back with its
+// FP64 norm partial (parts[tile]).  The next tile's first kBatchPrefetch
+// vectors per thread are loaded into registers while the current tile is
+// processed (as in the single-state pass kernel); the rest follow in batches.
+// Addresses of vectors past a small tile are clamped (every lane loads), and
+// only the LDS writes and global stores are predicated.
+constexpr int kBatchPrefetch = 4;
+
 template <typename R, bool WIDE>
-__device__ void run_tile(typename AmpOf<R>::A *psi, const PassDev &pd, uint64_t tileid, R sc,
-                         typename AmpOf<R>::A *tile, double *red, double *partial_out) {
+__device__ void run_tiles(typename AmpOf<R>::A *psi, const PassDev &pd, uint64_t t0, uint64_t t1, R sc,
+                          typename AmpOf<R>::A *tile, double *red, double *parts) {
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;
+    constexpr int PF = kBatchPrefetch;
     const PassArgs &pa = pd.pa;
     const uint32_t nvec = (1u << pa.t) / APV;
-    const uint64_t base = tile_base(tileid, pa);
-    for (uint32_t vi = threadIdx.x; vi < nvec; vi += TT) {
-        const uint32_t li = vi * APV;
-        float4 v = *reinterpret_cast<const float4 *>(psi + (base | tile_offset(li, pa)));
-        if constexpr (F32) {
-            v.x *= sc;
-            v.y *= sc;
-            v.z *= sc;
-            v.w *= sc;
-            *reinterpret_cast<float4 *>(tile + sw(li)) = v;
-        } else {
-            double2 d = *reinterpret_cast<double2 *>(&v);
-            d.x *= sc;
-            d.y *= sc;
-            tile[sw(li)] = d;
+    const uint32_t nj = (nvec + TT - 1) / TT;   // vectors per thread (uniform)
+    float4 pre[PF];
+    auto gptr = [&](uint64_t base, uint32_t j) {
+        uint32_t vi = threadIdx.x + j * TT;
+        vi = vi < nvec ? vi : nvec - 1;
+        return reinterpret_cast<float4 *>(psi + (base | tile_offset(vi * APV, pa)));
+    };
+    auto put = [&](uint32_t j, float4 v) {
+        const uint32_t vi = threadIdx.x + j * TT;
+        if (vi < nvec) {
+            if constexpr (F32) {
+                v.x *= sc;
+                v.y *= sc;
+                v.z *= sc;
+                v.w *= sc;
+                *reinterpret_cast<float4 *>(tile + sw(vi * APV)) = v;
+            } else {
+                double2 d = __builtin_bit_cast(double2, v);
+                d.x *= sc;
+                d.y *= sc;
+                tile[sw(vi)] = d;
+            }
         }
-    }
-    __syncthreads();
+    };
+    auto load_rest = [&](uint64_t base) {
+        for (uint32_t j0 = PF; j0 < nj; j0 += PF) {
+#pragma unroll
+            for (int i = 0; i < PF; ++i)
+                if (j0 + i < nj) pre[i] = *gptr(base, j0 + i);
+#pragma unroll
+            for (int i = 0; i < PF; ++i)
+                if (j0 + i < nj) put(j0 + i, pre[i]);
+        }
+    };
+    uint64_t tl = t0;
+    uint64_t base = tile_base(tl, pa);
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+        if ((uint32_t)j < nj) pre[j] = *gptr(base, j);
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+        if ((uint32_t)j < nj) put(j, pre[j]);
+    load_rest(base);
     const R *pool = reinterpret_cast<const R *>(pd.pool);
-    for (int b = 0; b < pa.nblocks; ++b) {
-        apply_block<R, WIDE>(tile, pa.t, pd.blocks + pa.block0 + b, pool);
+    for (;;) {
         __syncthreads();
-    }
-    double nacc = 0;
-    for (uint32_t vi = threadIdx.x; vi < nvec; vi += TT) {
-        const uint32_t li = vi * APV;
-        const float4 v = *reinterpret_cast<const float4 *>(tile + sw(li));
-        *reinterpret_cast<float4 *>(psi + (base | tile_offset(li, pa))) = v;
-        if constexpr (F32) {
-            nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
-        } else {
-            const double2 d = *reinterpret_cast<const double2 *>(&v);
-            nacc += d.x * d.x + d.y * d.y;
+        const uint64_t nxt = tl + 1;
+        const bool more = nxt < t1;   // uniform
+        const uint64_t nbase = more ? tile_base(nxt, pa) : base;
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+            if ((uint32_t)j < nj) pre[j] = *gptr(nbase, j);
+        for (int b = 0; b < pa.nblocks; ++b) {
+            apply_block<R, WIDE>(tile, pa.t, pd.blocks + pa.block0 + b, pool);
+            __syncthreads();
         }
+        double nacc = 0;
+        for (uint32_t j = 0; j < nj; ++j) {
+            const uint32_t vi = threadIdx.x + j * TT;
+            if (vi < nvec) {
+                const float4 v = *reinterpret_cast<const float4 *>(tile + sw(vi * APV));
+                *gptr(base, j) = v;
+                if constexpr (F32) {
+                    nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+                } else {
+                    const double2 d = __builtin_bit_cast(double2, v);
+                    nacc += d.x * d.x + d.y * d.y;
+                }
+            }
+        }
+        const double tot = wg_sum_values(nacc, red);   // ends with a barrier: the tile is free again
+        if (wave_id() == 0) parts[tl] = tot;  // same value from every lane of wave 0
+        if (!more) break;
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+            if ((uint32_t)j < nj) put(j, pre[j]);
+        load_rest(nbase);
+        tl = nxt;
+        base = nbase;
     }
-    const double tot = wg_sum_values(nacc, red);
-    if (wave_id() == 0) *partial_out = tot;  // same value from every lane of wave 0
 }
 
 __device__ __forceinline__ uint64_t ins0(uint64_t x, int p) {
@@ -174,40 +233,94 @@ __device__ __forceinline__ uint64_t ins0(uint64_t x, int p) {
     return ((x - lo) << 1) | lo;
 }
 
-// Re <psi|P|psi> restricted to pair indices [u0, u1) (x != 0) or amplitude
-// indices [u0, u1) (x == 0); same pairing as the single-state kernel.
-template <typename A>
-__device__ double pauli_partial(const A *psi, uint64_t x, uint64_t z, uint64_t u0, uint64_t u1) {
-    double s = 0;
-    if (x == 0) {
-        for (uint64_t j = u0 + threadIdx.x; j < u1; j += TT) {
-            const A a = psi[j];
-            const double m = (double)a.x * a.x + (double)a.y * a.y;
-            s += (__popcll(j & z) & 1) ? -m : m;
-        }
-        return s;
+// Expectation partials of kTermsPerItem Pauli terms over one amplitude chunk.
+// P = i^{n_Y} X^x Z^z (Y = i X Z on each qubit where x and z are both set)
+// maps |k> to i^{n_Y} (-1)^{popcount(k & z)} |k xor x>, so
+//   <psi|P|psi> = Re( i^{n_Y} sum_k (-1)^{popcount(k & z)} conj(psi[k xor x]) psi[k] ).
+// Each thread loads its own 16-byte vector once and gathers the partner
+// psi[k xor x] for every term of the group; products and sums are FP64.
+// Every lane runs the same number of iterations (vectors past the chunk are
+// clamped and weighted by zero): the persistent kernel has no lane-divergent
+// control flow.  Term t's sum over the chunk goes to out[t * stride].
+template <typename R>
+__device__ void energy_item(const typename AmpOf<R>::A *__restrict__ psi, int n, uint64_t chunk,
+                            const uint64_t *__restrict__ xs, const uint64_t *__restrict__ zs, uint32_t nterms,
+                            double *__restrict__ out, uint64_t stride, double *red) {
+    constexpr int G = kTermsPerItem;
+    constexpr uint32_t APV = sizeof(R) == 4 ? 2 : 1;
+    const uint64_t namps = 1ull << n;
+    const uint64_t C = namps < kAmpsPerItem ? namps : kAmpsPerItem;
+    const uint64_t a0 = chunk * C;
+    const uint32_t nv = (uint32_t)(C / APV);   // n >= 1, so C >= APV
+    const uint32_t iters = (nv + TT - 1) / TT;
+    uint64_t x[G], z[G];
+    double sg[G];   // +1 or -1: the real factor of i^{n_Y}
+    bool im[G];     // i^{n_Y} is imaginary: the term takes Im of the sum
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const bool ok = (uint32_t)g < nterms;
+        const int gi = ok ? g : 0;   // index 0 always exists (nterms >= 1): no load past the arrays
+        x[g] = ok ? xs[gi] : 0;
+        z[g] = ok ? zs[gi] : 0;
+        const int ny = __popcll(x[g] & z[g]) & 3;
+        im[g] = ny & 1;
+        sg[g] = (ny == 1 || ny == 2) ? -1.0 : 1.0;
     }
-    const int h = 63 - __clzll(x);
-    const int ny = __popcll(x & z) & 3;
-    for (uint64_t u = u0 + threadIdx.x; u < u1; u += TT) {
-        const uint64_t j = ins0(u, h), jp = j ^ x;
-        const A a = psi[j], b = psi[jp];
-        const double wr = (double)b.x * a.x + (double)b.y * a.y;
-        const double wi = (double)b.x * a.y - (double)b.y * a.x;
-        const double sj = (__popcll(j & z) & 1) ? -1.0 : 1.0;
-        const double sp = (__popcll(jp & z) & 1) ? -1.0 : 1.0;
-        switch (ny) {
-        case 0: s += (sj + sp) * wr; break;
-        case 1: s -= (sj - sp) * wi; break;
-        case 2: s -= (sj + sp) * wr; break;
-        default: s += (sj - sp) * wi; break;
+    double acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = 0.0;
+    for (uint32_t it = 0; it < iters; ++it) {
+        const uint32_t v = it * TT + threadIdx.x;
+        const double on = v < nv ? 1.0 : 0.0;
+        const uint64_t k0 = a0 + (uint64_t)(v < nv ? v : nv - 1) * APV;
+        if constexpr (APV == 2) {
+            const float4 own = reinterpret_cast<const float4 *>(psi)[k0 >> 1];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint64_t p0 = k0 ^ x[g];
+                const float4 pv = reinterpret_cast<const float4 *>(psi)[p0 >> 1];
+                const bool swp = p0 & 1;   // partner of amplitude k0 is the odd half
+                const double b0r = swp ? pv.z : pv.x, b0i = swp ? pv.w : pv.y;
+                const double b1r = swp ? pv.x : pv.z, b1i = swp ? pv.y : pv.w;
+                const double s0 = (__popcll(k0 & z[g]) & 1) ? -1.0 : 1.0;
+                const double s1 = (__popcll((k0 + 1) & z[g]) & 1) ? -1.0 : 1.0;
+                const double w0 = im[g] ? b0r * own.y - b0i * own.x : b0r * own.x + b0i * own.y;
+                const double w1 = im[g] ? b1r * own.w - b1i * own.z : b1r * own.z + b1i * own.w;
+                acc[g] += on * sg[g] * (s0 * w0 + s1 * w1);
+            }
+        } else {
+            const typename AmpOf<R>::A a = psi[k0];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const typename AmpOf<R>::A bb = psi[k0 ^ x[g]];
+                const double s0 = (__popcll(k0 & z[g]) & 1) ? -1.0 : 1.0;
+                const double w0 = im[g] ? (double)bb.x * a.y - (double)bb.y * a.x : (double)bb.x * a.x + (double)bb.y * a.y;
+                acc[g] += on * sg[g] * s0 * w0;
+            }
         }
     }
-    return s;
+    // fixed-order reduction: lanes (shuffles), then the waves in order
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc[g] += __shfl_xor(acc[g], o);
+        red[g * (TT / 64) + wave_id()] = acc[g];   // every lane holds the wave sum
+    }
+    __syncthreads();
+    if (wave_id() == 0) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double t = 0;
+#pragma unroll
+            for (int w = 0; w < TT / 64; ++w) t += red[g * (TT / 64) + w];
+            if ((uint32_t)g < nterms) out[g * stride] = t;   // same value from every lane
+        }
+    }
+    __syncthreads();
 }
 
 template <typename R, bool WIDE>
-__global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int nsegs, uint64_t total_items,
+__global__ __launch_bounds__(TT, WIDE ? 1 : 2) void k_batch(const Seg *__restrict__ segs, int nsegs, uint64_t total_items,
                                               const StateDev *__restrict__ states, const PassDev *__restrict__ passes,
                                               const uint64_t *__restrict__ xs, const uint64_t *__restrict__ zs,
                                               double *__restrict__ partials, double *__restrict__ eparts,
@@ -218,6 +331,7 @@ __global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *tile = reinterpret_cast<A *>(smem_raw);
     __shared__ double red[TT / 64];
+    __shared__ double ered[kTermsPerItem * (TT / 64)];
     __shared__ unsigned long long s_item;
     __shared__ int s_ok;
     const bool lane0 = (threadIdx.x & 63) == 0;
@@ -291,27 +405,24 @@ __global__ __launch_bounds__(TT) void k_batch(const Seg *__restrict__ segs, int 
                 const double N = wg_sum(partials + pd->prev_part_off, pd->prev_nparts, red);
                 sc = (R)(N > 0 ? 1.0 / sqrt(N) : 1.0);
             }
-            run_tile<R, WIDE>(psi, *pd, local, sc, tile, red, partials + pd->part_off + local);
+            const uint64_t t0 = local * pd->tiles_per_item;
+            const uint64_t t1 = t0 + pd->tiles_per_item < pd->ntiles ? t0 + pd->tiles_per_item : pd->ntiles;
+            run_tiles<R, WIDE>(psi, *pd, t0, t1, sc, tile, red, partials + pd->part_off);
             __syncthreads();
-            // ---- release: wave 0 publishes the finished tile ----
+            // ---- release: wave 0 publishes the finished tiles ----
             if (w0) {
                 __threadfence();
-                atomicAdd(done + sg.state, lane0 ? 1u : 0u);
+                atomicAdd(done + sg.state, lane0 ? (uint32_t)(t1 - t0) : 0u);
             }
         } else {
             // energy item: (term group, chunk)
-            const uint64_t npairs = (st.n >= 1) ? (1ull << (st.n - 1)) : 1;
             const uint64_t chunk = local % st.nchunks;
             const uint64_t tg = local / st.nchunks;
-            const uint64_t cl = npairs / st.nchunks;
-            for (uint32_t j = 0; j < st.terms_per_item; ++j) {
-                const uint64_t term = tg * st.terms_per_item + j;
-                if (term >= st.nterms) break;
-                const uint64_t x = xs[st.term0 + term], z = zs[st.term0 + term];
-                const uint64_t u0 = (x == 0 ? 2 : 1) * chunk * cl, u1 = u0 + (x == 0 ? 2 : 1) * cl;
-                const double tot = wg_sum_values(pauli_partial<A>(psi, x, z, u0, u1), red);
-                if (w0) eparts[st.epart0 + term * st.nchunks + chunk] = tot;
-            }
+            const uint64_t t0 = tg * kTermsPerItem;
+            const uint32_t left = st.nterms - (uint32_t)t0;
+            energy_item<R>(psi, st.n, chunk, xs + st.term0 + t0, zs + st.term0 + t0,
+                           left < (uint32_t)kTermsPerItem ? left : (uint32_t)kTermsPerItem,
+                           eparts + st.epart0 + t0 * st.nchunks + chunk, st.nchunks, ered);
         }
         __syncthreads();
     }
@@ -537,6 +648,8 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
             for (int j = 0; j < ps.t - ps.c; ++j) d.pa.hi[j] = ps.tile[ps.c + j];
             d.pa.want_norm = 1;
             d.ntiles = 1ull << (s.n - ps.t);
+            // items of up to 16 tiles, at least 4 items per pass when the pass has them
+            d.tiles_per_item = std::min<uint64_t>(16, std::max<uint64_t>(1, d.ntiles / 4));
             d.blocks = p.d_blocks[di];
             d.pool = p.d_pool[di];
             d.need_done = done_before;
@@ -557,9 +670,8 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
         s.last_nparts = prev_n;
         s.nterms = (uint32_t)n_terms[i];
         s.term0 = hx.size();
-        const uint64_t npairs = 1ull << (s.n - 1);
-        s.nchunks = (uint32_t)std::max<uint64_t>(1, npairs / kPairsPerItem);
-        s.terms_per_item = (uint32_t)std::max<uint64_t>(1, kPairsPerItem / npairs);
+        s.nchunks = (uint32_t)std::max<uint64_t>(1, (1ull << s.n) / kAmpsPerItem);
+        s.terms_per_item = (uint32_t)kTermsPerItem;
         s.epart0 = eparts;
         eparts += (uint64_t)s.nterms * s.nchunks;
         for (size_t k = 0; k < n_terms[i]; ++k) {
@@ -580,7 +692,8 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
     for (size_t pi = 0; pi < maxpasses; ++pi)
         for (int i = 0; i < n_states; ++i)
             if ((int)pi < sd[i].npasses) {
-                Seg s{item, pdv[sd[i].pass0 + pi].ntiles, i, kPassItem, (int32_t)pi, 0};
+                const PassDev &pd = pdv[sd[i].pass0 + pi];
+                Seg s{item, (pd.ntiles + pd.tiles_per_item - 1) / pd.tiles_per_item, i, kPassItem, (int32_t)pi, 0};
                 segs.push_back(s);
                 item += s.count;
             }
