@@ -411,6 +411,21 @@ def main():
         "roofline": roof,
     }
 
+    # ---- energy of the final state: a 200-term Pauli sum (outside the step) ----
+    ham = qsynth.random_pauli_sum(n, 200, seed=(7, 0))
+    Q.qs_profile_enable(True)
+    Q.qs_profile_collect()
+    t0 = time.perf_counter()
+    energy = st.expect(ham)
+    energy_s = time.perf_counter() - t0
+    pe = Q.qs_profile_collect()
+    Q.qs_profile_enable(False)
+    ex_ms = pe.ms[Q.PROF_EXPECT]
+    out["energy"] = {"terms": len(ham), "value": energy, "call_ms": round(energy_s * 1e3, 2),
+                     "kernel_ms": round(ex_ms, 2),
+                     "kernel_gbs": round(pe.bytes[Q.PROF_EXPECT] / (ex_ms * 1e-3) / 1e9, 1) if ex_ms > 0 else None,
+                     "bytes_per_term": "S (each amplitude read once per term)"}
+
     # ---- fused vs gate-by-gate on a prefix of the same circuit ----
     if a.plain_prefix > 0:
         # the generator draws exponentials in order, so this is the circuit's prefix
