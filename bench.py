@@ -84,13 +84,14 @@ def parse():
     ap.add_argument("--strategy", type=int, default=1)
     ap.add_argument("--plain-prefix", type=int, default=40,
                     help="Pauli exponentials timed gate-by-gate vs fused (0 = skip)")
-    ap.add_argument("--cpu-gates", type=int, default=12,
+    ap.add_argument("--cpu-gates", type=int, default=80,
                     help="gates of the circuit the FP64 oracle runs at full size (0 = skip)")
-    ap.add_argument("--mode", default="ucc", choices=["ucc", "copy", "batch", "learned", "brickwork"],
+    ap.add_argument("--mode", default="ucc", choices=["ucc", "copy", "batch", "learned", "brickwork", "plain12"],
                     help="ucc: the benchmark line; copy: device copy of one state-sized buffer "
                          "(achievable streaming bandwidth and counter calibration); batch: 256 HEA states "
                          "in one graph launch; learned: cost-model plan vs greedy at --n qubits; "
-                         "brickwork: 28-qubit brickwork, complex64 and complex128, plain vs fused")
+                         "brickwork: 28-qubit brickwork, complex64 and complex128, plain vs fused; "
+                         "plain12: 12-qubit random circuit, complex128, gate-by-gate vs the FP64 oracle")
     ap.add_argument("--states", type=int, default=256)
     return ap.parse_args()
 
@@ -152,8 +153,12 @@ def batch_mode(a):
         E = b.run()
     ms = (time.perf_counter() - t0) / a.steps * 1e3
     amps = sum(1 << c.n for c in circuits)
+    gbb = sum(plain_bytes(c, 8 << c.n) for c in circuits)
     out = {"mode": "batch", "states": a.states, "ms_per_batch": round(ms, 3),
            "states_per_s": round(a.states / (ms / 1e3), 1), "amplitudes": amps,
+           "circuits_effective_gbs": round(gbb / (ms * 1e-3) / 1e9, 1),
+           "note": "effective = the circuits' gate-by-gate bytes / batch time; the states are MALL-resident "
+                   "(cache-resident, not an HBM fraction)",
            "gates": sum(len(c) for c in circuits), "terms": sum(len(h) for h in hams),
            "create_s": round(create_s, 2), "energy_mean": float(np.mean(E))}
     # CPU baseline: the FP64 oracle on a sample of states (energy error of the GPU result)
@@ -257,7 +262,17 @@ def learned_mode(a):
         nl2 += float(np.vdot(al, al).real)
     fid = float(abs(dot) ** 2 / (ng2 * nl2))
     st2.close()
+    del st2
     progress(f"fidelity learned vs greedy {fid:.9f}")
+    # C followed by its inverse under the learned plan returns |0...0>; norm after renormalisation
+    both = qsynth.Circuit(n, list(c.gates) + list(qsynth.inverse(c).gates))
+    lb = Q.qs_contract(n, Q.GateList(both), Q.opts(strategy=Q.STRATEGY_LEARNED, **kw))
+    st.set_basis(0)
+    st.apply_plan(lb)
+    a0 = complex(Q.qs_state_copy_out(st.handle, 0, 1)[0])
+    norm_cc = st.norm()
+    Q.qs_plan_destroy(lb)
+    progress(f"C C^dagger |0>: |a0|^2 = {abs(a0) ** 2:.9f}, norm {norm_cc:.12f}")
     out = {"mode": "learned", "n": n, "gates": len(c), "greedy_config": kw, "autotune_s": round(tune_s, 1),
            "train_rows": int(len(y)), "train_loss": loss,
            "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
@@ -266,6 +281,7 @@ def learned_mode(a):
            "learned": {"passes": int(il.n_passes), "blocks": int(il.n_blocks), "ms": round(ms_l, 2),
                        "plan_s": round(tl_plan, 2)},
            "gain": round(ms_g / ms_l, 3), "fidelity_learned_vs_greedy": fid,
+           "c_cdagger_zero_prob": abs(a0) ** 2, "norm_after_c_cdagger": norm_cc,
            "k_max5": {"greedy_ms": round(ms_g5, 2), "learned_ms": round(ms_l5, 2), "gain": round(ms_g5 / ms_l5, 3)}}
     Q.qs_plan_destroy(greedy5)
     Q.qs_plan_destroy(learned5)
@@ -275,6 +291,46 @@ def learned_mode(a):
     print(json.dumps(out), flush=True)
 
 
+def plain12_mode(a):
+    """The plain method's configuration: 12-qubit random circuit (20 layers of
+    H or RZ per qubit + 6 CNOTs), complex128 from |0...0>, gate by gate.
+    GPU median of 5 runs; the FP64 oracle on 1 thread and on all threads."""
+    import numpy as np
+
+    import oracle
+    import qsynth
+    from paper_2509_04955_amd import qsim as Q
+
+    n = 12
+    c = qsynth.plain_random(n, 20, 6, seed=1)
+    gl = Q.GateList(c)
+    st = Q.State(n, Q.QS_C128)
+    times = [_timed(lambda: (st.set_basis(0), st.apply_gates(gl))) for _ in range(5)]
+    got = st.amplitudes()
+    st.close()
+    ref = oracle.run(c)
+    cpu = {}
+    threads = oracle.get_threads()
+    for th in (1, threads):
+        oracle.set_threads(th)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.run(c)
+            ts.append(time.perf_counter() - t0)
+        cpu[str(th)] = round(float(np.median(ts)) * 1e3, 3)
+    oracle.set_threads(threads)
+    S = 16 << n
+    ms = float(np.median(times))
+    print(json.dumps({"mode": "plain12", "n": n, "gates": len(c), "gpu_ms_median5": round(ms, 3),
+                      "gates_per_s": round(len(c) / (ms / 1e3), 1),
+                      "effective_gbs": round(plain_bytes(c, S) / (ms * 1e-3) / 1e9, 2),
+                      "max_abs_vs_fp64": float(np.max(np.abs(got - ref))),
+                      "cpu_baseline": {"value": round(cpu[str(threads)], 3), "unit": "ms", "cores": threads,
+                                       "kind": "oracle", "sample": "whole circuit, median of 3",
+                                       "one_thread_ms": cpu["1"]}}), flush=True)
+
+
 def brickwork_mode(a):
     """28-qubit brickwork (Haar U3 on every qubit + alternating CNOT pairs,
     depth 40): complex64 and complex128, gate-by-gate vs fused (k_max 5 or
@@ -282,10 +338,13 @@ def brickwork_mode(a):
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
+    import numpy as np
+
     n = min(a.n, 28)
     c = qsynth.brickwork(n, 40, seed=2)
     gl = Q.GateList(c)
     out = {"mode": "brickwork", "n": n, "gates": len(c)}
+    fused_amps = {}
     for dt, name in ((Q.QS_C64, "c64"), (Q.QS_C128, "c128")):
         best = Q.qs_autotune(n, dt, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
         print(f"[brickwork] {name}: autotuned k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits}",
@@ -303,8 +362,33 @@ def brickwork_mode(a):
                      "plain_effective_gbs": round(plain_bytes(c, S) / (ms_plain * 1e-3) / 1e9, 1),
                      "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1),
                      "fused_streamed_gbs": round((info.n_passes * 2 + 1) * S / (ms_fused * 1e-3) / 1e9, 1)}
+        st.set_basis(0)
+        st.apply_plan(plan)
+        fused_amps[name] = st.amplitudes()
         st.close()
         Q.qs_plan_destroy(plan)
+    # complex64 against the complex128 result (held to 1e-12 of the FP64 oracle by the parity tests)
+    a64, a128 = fused_amps["c64"], fused_amps["c128"]
+    out["c64_vs_c128"] = {"max_abs": float(np.max(np.abs(a64 - a128))),
+                          "one_minus_fidelity": float(1 - abs(np.vdot(a128, a64)) ** 2
+                                                      / (np.vdot(a64, a64).real * np.vdot(a128, a128).real))}
+    del fused_amps, a64, a128
+    # CPU baseline: the FP64 oracle on the circuit's first gates at full size, extrapolated
+    import oracle
+
+    psi = oracle.zero_state(n)
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(c) and time.perf_counter() - t0 < 15.0:
+        g = c.gates[k]
+        oracle.apply_gate(psi, n, g.name, g.qubits, g.params, g.matrix)
+        k += 1
+    cpu_s = time.perf_counter() - t0
+    del psi
+    out["cpu_baseline"] = {"value": round(cpu_s / k * len(c), 1), "unit": "s (extrapolated circuit time)",
+                           "cores": oracle.get_threads(), "kind": "oracle",
+                           "sample": f"first {k} of {len(c)} gates at n={n}, FP64 gate-by-gate ({cpu_s:.1f} s), "
+                                     "extrapolated linearly"}
     print(json.dumps(out), flush=True)
 
 
@@ -321,7 +405,8 @@ def main():
     torch.cuda.set_device(0)
     torch.cuda.init()
     if a.mode != "ucc":
-        {"copy": copy_mode, "batch": batch_mode, "learned": learned_mode, "brickwork": brickwork_mode}[a.mode](a)
+        {"copy": copy_mode, "batch": batch_mode, "learned": learned_mode, "brickwork": brickwork_mode,
+         "plain12": plain12_mode}[a.mode](a)
         return
     import numpy as np
 
