@@ -93,6 +93,8 @@ def parse():
                          "brickwork: 28-qubit brickwork, complex64 and complex128, plain vs fused; "
                          "plain12: 12-qubit random circuit, complex128, gate-by-gate vs the FP64 oracle")
     ap.add_argument("--states", type=int, default=256)
+    ap.add_argument("--train-n", type=int, default=28,
+                    help="learned mode: the cost model is trained on passes at this and one fewer qubit")
     return ap.parse_args()
 
 
@@ -207,7 +209,7 @@ def learned_mode(a):
     kw = dict(k_max=best.k_max, tile_qubits=best.tile_qubits, low_qubits=best.low_qubits)
     progress(f"autotuned greedy: k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits} ({tune_s:.0f} s)")
     train = []
-    for nt in sorted({min(n, 26), min(n, 28)}):
+    for nt in sorted({min(n, a.train_n - 1), min(n, a.train_n)}):
         train += [qsynth.random_u3_cnot(nt, 6, seed=31), qsynth.ucc(nt, 30, seed=32)[0],
                   qsynth.brickwork(nt, 6, seed=33), qsynth.hea(nt, 3, seed=(34, 0))]
     t0 = time.perf_counter()

@@ -148,13 +148,15 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds = true);
 // the monomial destinations when the block is monomial; lds: the pass stages
 // its operands in LDS (dense complex64 k = 3 then also runs on MFMA)
 int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds = false);
+// whether the single-state pass kernel stages this pass's block operands in LDS
+bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt);
 void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
                  std::vector<HPass> &out);
 void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks);
 int default_tile(qs_dtype dt);
 // learned.cpp: features of one pass (kNumFeatures floats) and the learned
 // per-window partition
-constexpr int kNumFeatures = 14;
+constexpr int kNumFeatures = 16;
 constexpr int kH1 = 64, kH2 = 64;
 constexpr int kNumWeights = kH1 * kNumFeatures + kH1 + kH2 * kH1 + kH2 + kH2 + 1;
 void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock> &blocks, float *out);

@@ -459,10 +459,10 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
 }
 
 // Pool bytes the blocks of a pass take when staged (the kinds of a staged pass).
-size_t pass_operand_bytes(const qs_plan_s &p, const HPass &ps, qs_dtype dt) {
+size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt) {
     size_t b = 0;
     for (int64_t i = ps.block0; i < ps.block0 + ps.nblocks; ++i) {
-        const HBlock &blk = p.blocks[i];
+        const HBlock &blk = blocks[i];
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
         size_t e = kind == BK_MONO   ? 4 * (size_t)D
@@ -506,6 +506,22 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     return BK_DENSE;
 }
 
+bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt) {
+    // stage the pass's operands in LDS when they fit and the pass has blocks
+    // that read per-lane operands (MFMA, wide monomial)
+    if (!staged_enabled()) return false;
+    const size_t budget = lds_operand_budget(ps.t, dt);
+    if (!budget) return false;
+    bool per_lane = false, dense_wide = false;
+    for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
+        const int k = (int)blocks[b].qubits.size();
+        const int kind = block_kind(blocks[b], ps.t, dt, nullptr, true);
+        per_lane |= kind == BK_MFMA || (kind == BK_MONO && k >= 4);
+        dense_wide |= kind == BK_DENSE && k > 3;
+    }
+    return per_lane && !dense_wide && pass_operand_bytes(blocks, ps, dt) <= budget;
+}
+
 qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
     const int di = dt == QS_C64 ? 0 : 1;
     if (p.dev_ready[di]) return QS_OK;
@@ -518,20 +534,7 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
     for (size_t pi = 0; pi < p.passes.size(); ++pi) {
         const HPass &ps = p.passes[pi];
         bool wide = false;
-        // stage the pass's operands in LDS when they fit and the pass has
-        // blocks that read per-lane operands (MFMA, wide monomial)
-        bool lds = false;
-        if (stage_lds && staged_enabled()) {
-            const size_t budget = lds_operand_budget(ps.t, dt);
-            bool per_lane = false, dense_wide = false;
-            for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
-                const int k = (int)p.blocks[b].qubits.size();
-                const int kind = block_kind(p.blocks[b], ps.t, dt, nullptr, true);
-                per_lane |= kind == BK_MFMA || (kind == BK_MONO && k >= 4);
-                dense_wide |= kind == BK_DENSE && k > 3;
-            }
-            lds = budget && per_lane && !dense_wide && pass_operand_bytes(p, ps, dt) <= budget;
-        }
+        const bool lds = stage_lds && pass_staged(p.blocks, ps, dt);
         const size_t pool0 = dt == QS_C64 ? pool32.size() : pool64.size();
         for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
             const HBlock &blk = p.blocks[b];

@@ -6,33 +6,40 @@
 // model trained on measured pass times:
 //   1. plan the circuit with the fixed-width greedy rule (width k_max) and
 //      take each of its passes as a window (the set of gates in that pass);
-//   2. re-contract every window's gates, in program order, with each width
-//      k = 1 .. kcap and pack the blocks into passes;
-//   3. predict every candidate pass's time with the MLP (device inference),
-//      and keep, per window, the width with the smallest predicted total.
+//   2. re-contract the gates of every run of 1..3 consecutive windows, in
+//      program order, with each width k = 1 .. kcap and pack the blocks into
+//      passes (a run can come out with fewer passes than windows);
+//   3. predict every candidate pass's time with the MLP (device inference)
+//      and cover the windows with the cheapest sequence of runs (dynamic
+//      programme); anything but the greedy width on a single window must
+//      beat it by a margin, so greedy stays where the model sees no clear gain.
 // Windows are contiguous ranges of a valid block order and the gates inside
 // a window keep their per-qubit order, so the resulting plan computes the
 // same state (exact arithmetic) as the circuit; only rounding differs.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 #include "internal.h"
 
 namespace qs {
 
 void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock> &blocks, float *f) {
-    int nd[4] = {0, 0, 0, 0}, n4 = 0, n5 = 0, nmono = 0, nwide = 0;
+    // block kinds as the pass kernel will run them (staged passes also put
+    // 3-qubit dense blocks on MFMA)
+    const bool staged = pass_staged(blocks, ps, dt);
+    int nd[4] = {0, 0, 0, 0}, n3m = 0, n4 = 0, n5 = 0, nmono = 0, nwide = 0;
     double flops = 0;
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
         const HBlock &blk = blocks[b];
         const int k = (int)blk.qubits.size();
-        const int kind = block_kind(blk, ps.t, dt, nullptr);
+        const int kind = block_kind(blk, ps.t, dt, nullptr, staged);
         if (kind == BK_MONO) {
             ++nmono;
             if (k > 4) ++nwide;
             flops += 6;
         } else if (kind == BK_MFMA) {
-            (k == 4 ? n4 : n5)++;
+            (k == 3 ? n3m : k == 4 ? n4 : n5)++;
             flops += 8.0 * (1 << k);
         } else {
             if (k <= 3) ++nd[k];
@@ -54,15 +61,26 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
     f[11] = nwide / 8.0f;
     f[12] = (float)(std::log2(1.0 + flops) / 10.0);
     f[13] = (float)(ps.nblocks > 0 ? std::log2(1.0 + flops / ps.nblocks) / 10.0 : 0.0);
+    f[14] = staged ? 1.0f : 0.0f;
+    f[15] = n3m / 8.0f;
 }
 
 namespace {
 
 struct Candidate {
+    int k = 0;                    // fusion width of this re-contraction
+    int span = 1;                 // consecutive windows it covers
     std::vector<HBlock> blocks;   // member indices are global gate indices
     std::vector<HPass> passes;    // block0 relative to `blocks`
     double cost = 0;
 };
+
+// A window leaves the greedy width only for a predicted gain of at least this
+// fraction: the greedy plan is the fallback, and the model's error on a
+// single window is of that order.
+constexpr double kSwitchMargin = 0.03;
+// Longest run of consecutive greedy windows re-contracted as one candidate.
+constexpr int kMaxSpan = 3;
 
 }  // namespace
 
@@ -83,51 +101,87 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
             window[w].insert(window[w].end(), ref[b].members.begin(), ref[b].members.end());
         std::sort(window[w].begin(), window[w].end());
     }
-    // 2. candidates per window and width
+    // 2. candidates: runs of 1..kMaxSpan consecutive windows re-contracted
+    //    together at every width (the run's gates in program order)
     int wgate = 1;
     for (const HGate &g : p.gates) wgate = std::max(wgate, g.nq);
-    std::vector<std::vector<Candidate>> cand(nw);
+    std::vector<std::vector<Candidate>> cand(nw);   // cand[e]: runs ending at window e
     std::vector<float> feats;
-    std::vector<std::pair<size_t, size_t>> owner;  // (window, candidate) of each feature row
-    for (size_t w = 0; w < nw; ++w) {
-        std::vector<HGate> sub;
-        sub.reserve(window[w].size());
-        for (int64_t gi : window[w]) sub.push_back(p.gates[gi]);
-        for (int k = 1; k <= kcap; ++k) {
-            if (t < p.n && std::max(k, wgate) > t - 1) continue;
-            Candidate cd;
-            greedy_blocks(sub, p.n, k, cd.blocks);
-            for (HBlock &b : cd.blocks) {
-                block_matrix(sub, b);
-                for (int64_t &m : b.members) m = window[w][m];
+    std::vector<std::pair<size_t, size_t>> owner;  // (end window, candidate) of each feature row
+    for (size_t e = 0; e < nw; ++e) {
+        for (int r = 1; r <= kMaxSpan && (size_t)r <= e + 1; ++r) {
+            std::vector<int64_t> gids;
+            for (size_t w = e + 1 - r; w <= e; ++w) gids.insert(gids.end(), window[w].begin(), window[w].end());
+            std::sort(gids.begin(), gids.end());
+            std::vector<HGate> sub;
+            sub.reserve(gids.size());
+            for (int64_t gi : gids) sub.push_back(p.gates[gi]);
+            for (int k = 1; k <= kcap; ++k) {
+                if (t < p.n && std::max(k, wgate) > t - 1) continue;
+                if (r > 1 && k == o.k_max) continue;   // the greedy width over several windows is the windows themselves
+                Candidate cd;
+                cd.k = k;
+                cd.span = r;
+                greedy_blocks(sub, p.n, k, cd.blocks);
+                for (HBlock &b : cd.blocks) {
+                    block_matrix(sub, b);   // for the block kinds in the features; dropped below
+                    for (int64_t &m : b.members) m = gids[m];
+                }
+                pack_passes(p, cd.blocks, t, c, cd.passes);
+                for (const HPass &ps : cd.passes) {
+                    feats.resize(feats.size() + kNumFeatures);
+                    pass_features(p.n, dt, ps, cd.blocks, feats.data() + feats.size() - kNumFeatures);
+                    owner.push_back({e, cand[e].size()});
+                }
+                for (HBlock &b : cd.blocks) {
+                    b.U.clear();
+                    b.U.shrink_to_fit();
+                }
+                cand[e].push_back(std::move(cd));
             }
-            pack_passes(p, cd.blocks, t, c, cd.passes);
-            for (const HPass &ps : cd.passes) {
-                feats.resize(feats.size() + kNumFeatures);
-                pass_features(p.n, dt, ps, cd.blocks, feats.data() + feats.size() - kNumFeatures);
-                owner.push_back({w, cand[w].size()});
-            }
-            cand[w].push_back(std::move(cd));
         }
     }
-    // 3. predicted cost (device inference) and choice
+    // 3. predicted cost (device inference), then the cheapest cover of the
+    //    windows by runs (dynamic programme).  A run other than a single
+    //    window at the greedy width pays a margin: the greedy plan is the
+    //    fallback where the model predicts no clear gain.
     std::vector<float> pred(owner.size());
     qs_status st = costmodel_predict_device(feats.data(), (int)owner.size(), pred.data());
     if (st != QS_OK) return st;
     for (size_t r = 0; r < owner.size(); ++r) cand[owner[r].first][owner[r].second].cost += std::exp((double)pred[r]);
+    std::vector<double> best(nw + 1, 0.0);
+    std::vector<size_t> pick(nw, 0);
+    for (size_t e = 0; e < nw; ++e) {
+        best[e + 1] = std::numeric_limits<double>::infinity();
+        for (size_t i = 0; i < cand[e].size(); ++i) {
+            const Candidate &cd = cand[e][i];
+            const bool greedy = cd.span == 1 && cd.k == o.k_max;
+            const double v = best[e + 1 - cd.span] + cd.cost * (greedy ? 1.0 : 1.0 / (1.0 - kSwitchMargin));
+            if (v < best[e + 1]) {
+                best[e + 1] = v;
+                pick[e] = i;
+            }
+        }
+    }
+    std::vector<Candidate *> chosen;
+    for (size_t e = nw; e > 0;) {
+        Candidate &cd = cand[e - 1][pick[e - 1]];
+        chosen.push_back(&cd);
+        e -= (size_t)cd.span;
+    }
+    std::reverse(chosen.begin(), chosen.end());
     p.blocks.clear();
     p.passes.clear();
-    for (size_t w = 0; w < nw; ++w) {
-        size_t best = 0;
-        for (size_t i = 1; i < cand[w].size(); ++i)
-            if (cand[w][i].cost < cand[w][best].cost) best = i;
-        Candidate &cd = cand[w][best];
+    for (Candidate *cd : chosen) {
         const int64_t off = (int64_t)p.blocks.size();
-        for (HPass ps : cd.passes) {
+        for (HPass ps : cd->passes) {
             ps.block0 += off;
             p.passes.push_back(std::move(ps));
         }
-        for (HBlock &b : cd.blocks) p.blocks.push_back(std::move(b));
+        for (HBlock &b : cd->blocks) {
+            block_matrix(p.gates, b);
+            p.blocks.push_back(std::move(b));
+        }
     }
     return QS_OK;
 }
