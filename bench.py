@@ -226,6 +226,15 @@ def learned_mode(a):
     train_s = time.perf_counter() - t0
     corr = float(np.corrcoef(CM.predict(X), y)[0, 1])
     progress(f"trained on {len(y)} passes: loss {loss:.4f}, corr {corr:.3f}")
+    # two rounds on the model's own choices, on held-out circuits of the
+    # benchmark family (seed 6, not the evaluated seed 5) at train_n + 2 qubits
+    t0 = time.perf_counter()
+    n_ref = min(n, a.train_n + 2)
+    ref_circuits = [qsynth.random_u3_cnot(n_ref, 30, seed=6)]
+    X, y, loss = CM.refine(X, y, ref_circuits, rounds=2, **kw)
+    refine_s = time.perf_counter() - t0
+    corr = float(np.corrcoef(CM.predict(X), y)[0, 1])
+    progress(f"refined on the learned plans' own passes: {len(y)} rows, loss {loss:.4f}, corr {corr:.3f}")
     t0 = time.perf_counter()
     greedy = Q.qs_contract(n, gl, Q.opts(**kw))
     tg_plan = time.perf_counter() - t0
@@ -276,7 +285,7 @@ def learned_mode(a):
     Q.qs_plan_destroy(lb)
     progress(f"C C^dagger |0>: |a0|^2 = {abs(a0) ** 2:.9f}, norm {norm_cc:.12f}")
     out = {"mode": "learned", "n": n, "gates": len(c), "greedy_config": kw, "autotune_s": round(tune_s, 1),
-           "train_rows": int(len(y)), "train_loss": loss,
+           "train_rows": int(len(y)), "train_loss": loss, "refine_s": round(refine_s, 1),
            "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
            "greedy": {"passes": int(ig.n_passes), "blocks": int(ig.n_blocks), "ms": round(ms_g, 2),
                       "plan_s": round(tg_plan, 2)},

@@ -73,6 +73,31 @@ def target(us: np.ndarray, X: np.ndarray) -> np.ndarray:
     return (np.log(us) - (n - 30.0) * math.log(2.0)).astype(np.float32)
 
 
+def refine(X: np.ndarray, y: np.ndarray, circuits, rounds: int = 2, reps: int = 3, epochs: int = 300,
+           batch: int = 64, lr: float = 3e-3, seed: int = 1, dtype: int = Q.QS_C64, **plan_opts):
+    """Train on the model's own choices: plan each circuit with the learned
+    strategy under the active model, time every pass of that plan, add those
+    rows to (X, y) and retrain; `rounds` times.  The passes the learned
+    partition proposes are the ones the fixed-width sweep in collect() rarely
+    contains.  Returns the grown (X, y) and the last training loss."""
+    loss = None
+    for r in range(rounds):
+        xs, ys = [X], [y]
+        for c in circuits:
+            plan = Q.qs_contract(c.n, Q.GateList(c), Q.opts(strategy=Q.STRATEGY_LEARNED, dtype=dtype, **plan_opts))
+            try:
+                f = pass_features(plan)
+                us = time_passes(plan, dtype, reps)
+            finally:
+                Q.qs_plan_destroy(plan)
+            xs.append(f)
+            ys.append(target(us, f))
+        X = np.concatenate(xs).astype(np.float32)
+        y = np.concatenate(ys).astype(np.float32)
+        loss = train(X, y, epochs=epochs, batch=batch, lr=lr, seed=seed + r + 1)
+    return X, y, loss
+
+
 def train(X: np.ndarray, y: np.ndarray, epochs: int = 400, batch: int = 64, lr: float = 3e-3, seed: int = 1):
     """Train on the device; the trained model becomes the active one."""
     X = np.ascontiguousarray(X, dtype=np.float32)
