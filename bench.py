@@ -86,12 +86,14 @@ def parse():
                     help="Pauli exponentials timed gate-by-gate vs fused (0 = skip)")
     ap.add_argument("--cpu-gates", type=int, default=80,
                     help="gates of the circuit the FP64 oracle runs at full size (0 = skip)")
-    ap.add_argument("--mode", default="ucc", choices=["ucc", "copy", "batch", "learned", "brickwork", "plain12"],
+    ap.add_argument("--mode", default="ucc",
+                    choices=["ucc", "copy", "batch", "learned", "brickwork", "plain12", "families"],
                     help="ucc: the benchmark line; copy: device copy of one state-sized buffer "
                          "(achievable streaming bandwidth and counter calibration); batch: 256 HEA states "
                          "in one graph launch; learned: cost-model plan vs greedy at --n qubits; "
                          "brickwork: 28-qubit brickwork, complex64 and complex128, plain vs fused; "
-                         "plain12: 12-qubit random circuit, complex128, gate-by-gate vs the FP64 oracle")
+                         "plain12: 12-qubit random circuit, complex128, gate-by-gate vs the FP64 oracle; "
+                         "families: the paper's circuit families (HEA, QAOA, QFT) at 20/25/30 qubits")
     ap.add_argument("--states", type=int, default=256)
     ap.add_argument("--train-n", type=int, default=28,
                     help="learned mode: the cost model is trained on passes at this and one fewer qubit")
@@ -342,6 +344,42 @@ def plain12_mode(a):
                                        "one_thread_ms": cpu["1"]}}), flush=True)
 
 
+def families_mode(a):
+    """The paper's circuit families at 20, 25 and 30 qubits, complex64: HEA
+    (5 layers RX/RY/RZ + staggered CNOT), QAOA MaxCut (3-regular graph, p = 3)
+    and QFT.  Gate-count compression of the contraction at k_max = 2 and at
+    the autotuned width, gate-by-gate vs fused time."""
+    import qsynth
+    from paper_2509_04955_amd import qsim as Q
+
+    rows = []
+    for n in (20, 25, 30):
+        for name, c in (("hea", qsynth.hea_rxyz(n)), ("qaoa", qsynth.qaoa_maxcut(n)), ("qft", qsynth.qft(n))):
+            gl = Q.GateList(c)
+            p2 = Q.qs_contract(n, gl, Q.opts(k_max=2))
+            b2 = int(Q.qs_plan_info_get(p2).n_blocks)
+            Q.qs_plan_destroy(p2)
+            best = Q.qs_autotune(n, Q.QS_C64, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
+            plan = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
+                                               low_qubits=best.low_qubits))
+            info = Q.qs_plan_info_get(plan)
+            st = Q.State(n, Q.QS_C64)
+            ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
+            ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
+            st.close()
+            Q.qs_plan_destroy(plan)
+            S = 8 << n
+            rows.append({"family": name, "n": n, "gates": len(c),
+                         "compression_k2": round(1 - b2 / len(c), 4),
+                         "k_max": best.k_max, "blocks": int(info.n_blocks),
+                         "compression": round(1 - info.n_blocks / len(c), 4), "passes": int(info.n_passes),
+                         "plain_ms": round(ms_plain, 2), "fused_ms": round(ms_fused, 2),
+                         "speedup": round(ms_plain / ms_fused, 2),
+                         "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1)})
+            print(f"[families] {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "families", "rows": rows}), flush=True)
+
+
 def brickwork_mode(a):
     """28-qubit brickwork (Haar U3 on every qubit + alternating CNOT pairs,
     depth 40): complex64 and complex128, gate-by-gate vs fused (k_max 5 or
@@ -417,7 +455,7 @@ def main():
     torch.cuda.init()
     if a.mode != "ucc":
         {"copy": copy_mode, "batch": batch_mode, "learned": learned_mode, "brickwork": brickwork_mode,
-         "plain12": plain12_mode}[a.mode](a)
+         "plain12": plain12_mode, "families": families_mode}[a.mode](a)
         return
     import numpy as np
 

@@ -191,6 +191,53 @@ def hea(n: int, layers: int = 8, seed=(4, 0)) -> Circuit:
     return c
 
 
+def hea_rxyz(n: int, layers: int = 5, seed=(8, 0)) -> Circuit:
+    """The paper's HEA shape: per layer RX, RY, RZ (theta ~ U[0,2pi)) on every
+    qubit, then staggered CNOTs (0,1),(2,3),... on even layers and
+    (1,2),(3,4),... on odd layers."""
+    rng = _rng(*seed) if isinstance(seed, tuple) else _rng(seed)
+    c = Circuit(n)
+    for layer in range(layers):
+        for name in ("rx", "ry", "rz"):
+            for q in range(n):
+                c.add(name, (q,), (rng.random() * 2 * math.pi,))
+        for q in range(layer % 2, n - 1, 2):
+            c.add("cx", (q, q + 1))
+    return c
+
+
+def random_regular_edges(rng: np.random.Generator, n: int, degree: int = 3):
+    """Edges of a random `degree`-regular simple graph on n vertices (n*degree
+    even), by the configuration model with restarts."""
+    assert (n * degree) % 2 == 0 and degree < n
+    while True:
+        stubs = rng.permutation(np.repeat(np.arange(n), degree))
+        pairs = stubs.reshape(-1, 2)
+        edges = {tuple(sorted((int(a), int(b)))) for a, b in pairs}
+        if all(a != b for a, b in pairs) and len(edges) == len(pairs):
+            return sorted(edges)
+
+
+def qaoa_maxcut(n: int, p: int = 3, seed=(9, 0)) -> Circuit:
+    """QAOA for MaxCut on a random 3-regular graph: H on every qubit, then p
+    rounds of exp(-i gamma Z_a Z_b) per edge (CNOT, RZ(2 gamma), CNOT) and
+    RX(2 beta) on every qubit; gamma, beta ~ U[0, pi)."""
+    rng = _rng(*seed) if isinstance(seed, tuple) else _rng(seed)
+    edges = random_regular_edges(rng, n, 3 if n % 2 == 0 else 2)
+    c = Circuit(n)
+    for q in range(n):
+        c.add("h", (q,))
+    for _ in range(p):
+        gamma, beta = rng.random() * math.pi, rng.random() * math.pi
+        for a, b in edges:
+            c.add("cx", (a, b))
+            c.add("rz", (b,), (2 * gamma,))
+            c.add("cx", (a, b))
+        for q in range(n):
+            c.add("rx", (q,), (2 * beta,))
+    return c
+
+
 def random_pauli_sum(n: int, n_terms: int = 200, seed=(5, 0)) -> PauliSum:
     """Per term and qubit a letter uniform in {I, X, Y, Z}; coeff ~ N(0, 1)."""
     rng = _rng(*seed) if isinstance(seed, tuple) else _rng(seed)

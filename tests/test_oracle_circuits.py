@@ -113,3 +113,35 @@ def test_rz_only_phases(oracle):
     for q in range(n):
         ph += -0.5 * thetas[q] * (1 - 2 * ((idx >> q) & 1))
     assert np.max(np.abs(psi - np.exp(1j * ph) * psi0)) < 1e-14
+
+
+def test_qaoa_state_is_invariant_under_global_flip(oracle):
+    """QAOA for MaxCut starts from |+>^n and uses ZZ costs and an RX mixer,
+    all of which commute with X on every qubit, so psi[k] = psi[~k]."""
+    n = 10
+    c = qsynth.qaoa_maxcut(n, p=2, seed=(3, 1))
+    psi = oracle.run(c)
+    full = (1 << n) - 1
+    idx = np.arange(1 << n)
+    assert np.max(np.abs(psi - psi[idx ^ full])) <= 1e-12
+    assert abs(np.vdot(psi, psi).real - 1) <= 1e-12
+
+
+def test_qaoa_graph_is_three_regular():
+    rng = np.random.default_rng(4)
+    edges = qsynth.random_regular_edges(rng, 12, 3)
+    deg = np.zeros(12, dtype=int)
+    for a, b in edges:
+        assert a != b
+        deg[a] += 1
+        deg[b] += 1
+    assert len(set(edges)) == len(edges) == 18 and np.all(deg == 3)
+
+
+def test_hea_rxyz_shape_and_norm(oracle):
+    n, layers = 9, 5
+    c = qsynth.hea_rxyz(n, layers, seed=(2, 2))
+    ncx = sum(len(range(l % 2, n - 1, 2)) for l in range(layers))
+    assert len(c) == layers * 3 * n + ncx
+    psi = oracle.run(c)
+    assert abs(np.vdot(psi, psi).real - 1) <= 1e-12
