@@ -597,6 +597,10 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
             }
             o = it->second;
         }
+        // The batch kernel applies complex128 blocks wider than 3 qubits on the
+        // vector ALU in its wide variant (no staged FP64 MFMA there), which the
+        // single-state timings of the autotuner do not see: keep them narrow.
+        if (dt == QS_C128 && (base.k_max == 0 || base.tile_qubits == 0)) o.k_max = std::min(o.k_max, 3);
         qs_plan p = nullptr;
         qs_status st = qs_contract(n_qubits[i], circuits[i], n_gates[i], &o, &p);
         if (st != QS_OK) {
