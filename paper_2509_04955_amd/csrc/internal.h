@@ -48,13 +48,14 @@ enum : int32_t {
     BK_DENSE = 0,   // vector ALU, full 2^k x 2^k complex matrix
     BK_MFMA = 1,    // complex64, k = 4 or 5: MFMA with a pre-swizzled A operand
     BK_MONO = 2,    // monomial (one nonzero per column): y[dest(c)] = u_c x[c]
+    BK_BDIAG = 3,   // permuted block-diagonal: classes of 2^sub rows/columns
 };
 
 struct BlockDev {
     int32_t k;          // width
     int32_t kind;       // BK_*
     int32_t mat_off;    // offset (reals) of the matrix data in the plan's pool
-    int32_t pad;
+    int32_t sub;        // BK_BDIAG: log2 of the class width, else 0
     int32_t pos[kMaxK]; // tile positions (ascending) of the block's qubits
     int32_t pad2[2];
 };
@@ -148,15 +149,18 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds = true);
 // the monomial destinations when the block is monomial; lds: the pass stages
 // its operands in LDS (dense complex64 k = 3 then also runs on MFMA)
 int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds = false);
+// log2 of the class width of a block's permuted block-diagonal form (BK_BDIAG)
+int bdiag_log_width(const HBlock &b);
 // whether the single-state pass kernel stages this pass's block operands in LDS
 bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt);
-void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
+// packs blocks into passes and reorders them into execution order (in place)
+void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c,
                  std::vector<HPass> &out);
 void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks);
 int default_tile(qs_dtype dt);
 // learned.cpp: features of one pass (kNumFeatures floats) and the learned
 // per-window partition
-constexpr int kNumFeatures = 16;
+constexpr int kNumFeatures = 17;
 constexpr int kH1 = 64, kH2 = 64;
 constexpr int kNumWeights = kH1 * kNumFeatures + kH1 + kH2 * kH1 + kH2 + kH2 + 1;
 void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock> &blocks, float *out);

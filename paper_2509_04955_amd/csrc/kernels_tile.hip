@@ -414,6 +414,83 @@ bool structured_enabled() {
     return v == 1;
 }
 
+// Permuted block-diagonal structure: the bipartite graph of U's nonzero
+// entries (rows against columns) splits into connected components, each with
+// as many rows as columns (U is unitary).  The components are packed (largest
+// first, first fit) into 2^(k-s) classes of exactly 2^s rows and 2^s
+// columns, with the smallest s that packs; U then acts as 2^(k-s)
+// independent 2^s x 2^s matrices between the classes' column and row lists.
+// src lists the columns class by class, dst the rows in the same order.
+bool bdiag_split(const std::vector<cd> &U, int k, int &s, std::vector<int> &src, std::vector<int> &dst) {
+    const int D = 1 << k;
+    std::vector<int> parent(2 * D);
+    for (int i = 0; i < 2 * D; ++i) parent[i] = i;
+    auto find = [&](int x) {
+        while (parent[x] != x) x = parent[x] = parent[parent[x]];
+        return x;
+    };
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c)
+            if (std::abs(U[(size_t)r * D + c]) > kZeroTol) parent[find(r)] = find(D + c);
+    std::vector<std::vector<int>> rows(2 * D), cols(2 * D);
+    for (int r = 0; r < D; ++r) rows[find(r)].push_back(r);
+    for (int c = 0; c < D; ++c) cols[find(D + c)].push_back(c);
+    std::vector<int> comps;
+    size_t widest = 1;
+    for (int i = 0; i < 2 * D; ++i) {
+        if (rows[i].size() != cols[i].size()) return false;
+        if (!rows[i].empty()) {
+            comps.push_back(i);
+            widest = std::max(widest, rows[i].size());
+        }
+    }
+    std::stable_sort(comps.begin(), comps.end(), [&](int a, int b) { return rows[a].size() > rows[b].size(); });
+    for (s = 0; (size_t)1 << s < widest; ++s) {}
+    for (; s <= k; ++s) {
+        const int DS = 1 << s, NC = D / DS;
+        std::vector<std::vector<int>> br(NC), bc(NC);
+        bool ok = true;
+        for (int cp : comps) {
+            int j = 0;
+            while (j < NC && br[j].size() + rows[cp].size() > (size_t)DS) ++j;
+            if (j == NC) {
+                ok = false;
+                break;
+            }
+            br[j].insert(br[j].end(), rows[cp].begin(), rows[cp].end());
+            bc[j].insert(bc[j].end(), cols[cp].begin(), cols[cp].end());
+        }
+        if (!ok) continue;
+        src.clear();
+        dst.clear();
+        for (int j = 0; j < NC; ++j) {
+            src.insert(src.end(), bc[j].begin(), bc[j].end());
+            dst.insert(dst.end(), br[j].begin(), br[j].end());
+        }
+        return true;
+    }
+    return false;
+}
+
+// Class widths the tile kernel has permuted block-diagonal code for:
+// 1 <= s < k, k = 3 or 4 (a lane holds the whole group: 2^5 amplitudes would
+// not fit beside the prefetched tile); QS_TILE_BDIAG = 0 turns the kind off,
+// a value g > 1 keeps it to s <= k - g.
+int bdiag_gap() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_TILE_BDIAG");
+        v = e ? std::max(0, atoi(e)) : 1;
+    }
+    return v;
+}
+
+bool bdiag_supported(int k, int s, qs_dtype dt) {
+    const int gap = bdiag_gap();
+    (void)dt;
+    return gap > 0 && k >= 3 && k <= 4 && s >= 1 && s <= k - gap;
+}
+
 bool staged_enabled() {
     static int v = -1;
     if (v < 0) {
@@ -428,7 +505,32 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
     const int D = 1 << d.k;
     std::vector<int> dest;
     const int kind = block_kind(blk, t, dt, &dest, lds);
-    if (kind == BK_MONO) {
+    if (kind == BK_BDIAG) {
+        // record: 2^k swizzled source offsets (class by class), 2^k swizzled
+        // destination offsets, then the classes' 2^s x 2^s matrices
+        int sub = 0;
+        std::vector<int> src, dst;
+        bdiag_split(blk.U, d.k, sub, src, dst);
+        d.kind = BK_BDIAG;
+        d.sub = sub;
+        d.mat_off = (int32_t)pool.size();
+        auto deposit = [&](int c) {
+            uint32_t o = 0;
+            for (int j = 0; j < d.k; ++j)
+                if ((c >> j) & 1) o |= 1u << d.pos[j];
+            return sw(o);
+        };
+        for (int i = 0; i < D; ++i) pool.push_back((R)deposit(src[i]));
+        for (int i = 0; i < D; ++i) pool.push_back((R)deposit(dst[i]));
+        const int DS = 1 << sub;
+        for (int j = 0; j < D / DS; ++j)
+            for (int r = 0; r < DS; ++r)
+                for (int c = 0; c < DS; ++c) {
+                    const cd u = blk.U[(size_t)dst[j * DS + r] * D + src[j * DS + c]];
+                    pool.push_back((R)u.real());
+                    pool.push_back((R)u.imag());
+                }
+    } else if (kind == BK_MONO) {
         d.kind = BK_MONO;
         d.mat_off = (int32_t)pool.size();
         for (int c = 0; c < D; ++c) {
@@ -458,6 +560,21 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
     while (pool.size() % 4) pool.push_back((R)0);  // 16-byte aligned entries
 }
 
+// Class width 2^s of a permuted block-diagonal block.
+size_t bdiag_width(const HBlock &b) {
+    int sub = 0;
+    std::vector<int> src, dst;
+    bdiag_split(b.U, (int)b.qubits.size(), sub, src, dst);
+    return (size_t)1 << sub;
+}
+
+// Real flops per amplitude of one block as the tile kernel applies it.
+double block_flops_per_amp(const BlockDev &d) {
+    if (d.kind == BK_MONO) return 6.0;
+    if (d.kind == BK_BDIAG) return 8.0 * (1 << d.sub);
+    return 8.0 * (1 << d.k);
+}
+
 // Pool bytes the blocks of a pass take when staged (the kinds of a staged pass).
 size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt) {
     size_t b = 0;
@@ -465,9 +582,10 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
         const HBlock &blk = blocks[i];
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
-        size_t e = kind == BK_MONO   ? 4 * (size_t)D
-                   : kind == BK_MFMA ? (k >= 4 ? (size_t)3 * D * D : (size_t)4 * D * D)
-                                     : 2 * (size_t)D * D;
+        size_t e = kind == BK_MONO    ? 4 * (size_t)D
+                   : kind == BK_MFMA  ? (k >= 4 ? (size_t)3 * D * D : (size_t)4 * D * D)
+                   : kind == BK_BDIAG ? 2 * (size_t)D + 2 * (size_t)D * bdiag_width(blk)
+                                      : 2 * (size_t)D * D;
         e = (e + 3) / 4 * 4;
         b += e * (dt == QS_C64 ? 4 : 8);
     }
@@ -497,6 +615,13 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     const int k = (int)b.qubits.size();
     std::vector<int> tmp;
     if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp)) return BK_MONO;
+    // permuted block-diagonal: 2^s complex multiply-adds per amplitude on the
+    // vector ALU instead of a dense product
+    int sub = 0;
+    std::vector<int> src, dst;
+    if (structured_enabled() && bdiag_gap() > 0 && k >= 3 && bdiag_split(b.U, k, sub, src, dst) &&
+        bdiag_supported(k, sub, dt))
+        return BK_BDIAG;
     // complex64: MFMA for k = 4, 5 (k = 3 too when staged); complex128: FP64
     // MFMA only in staged passes (the unstaged FP64 path is the vector ALU)
     if (t - k >= 4 && mfma_enabled()) {
@@ -504,6 +629,12 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
         if (dt == QS_C128 && lds && k >= 3 && k <= 5) return BK_MFMA;
     }
     return BK_DENSE;
+}
+
+int bdiag_log_width(const HBlock &b) {
+    int sub = 0;
+    std::vector<int> src, dst;
+    return bdiag_split(b.U, (int)b.qubits.size(), sub, src, dst) ? sub : (int)b.qubits.size();
 }
 
 bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt) {
@@ -615,8 +746,7 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     const double S = std::ldexp((double)amp, s.n);
     double flops = 0;
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b)
-        flops += (p.h_blocks[di][b].kind == BK_MONO ? 6.0 : 8.0 * std::ldexp(1.0, p.h_blocks[di][b].k)) *
-                 std::ldexp(1.0, s.n);
+        flops += block_flops_per_amp(p.h_blocks[di][b]) * std::ldexp(1.0, s.n);
     prof_begin(s.stream, QS_PROF_TILE, 2 * S, flops);
     if (s.dtype == QS_C64)
         hipLaunchKernelGGL(pick_tile_kernel<float>(wide, ps.t, cl), grid, dim3(TT), lds, s.stream, (float2 *)s.amp, ntiles,

@@ -28,7 +28,7 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
     // block kinds as the pass kernel will run them (staged passes also put
     // 3-qubit dense blocks on MFMA)
     const bool staged = pass_staged(blocks, ps, dt);
-    int nd[4] = {0, 0, 0, 0}, n3m = 0, n4 = 0, n5 = 0, nmono = 0, nwide = 0;
+    int nd[4] = {0, 0, 0, 0}, n3m = 0, n4 = 0, n5 = 0, nmono = 0, nwide = 0, nbd = 0;
     double flops = 0;
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
         const HBlock &blk = blocks[b];
@@ -38,6 +38,9 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
             ++nmono;
             if (k > 4) ++nwide;
             flops += 6;
+        } else if (kind == BK_BDIAG) {
+            ++nbd;
+            flops += 8.0 * (1 << bdiag_log_width(blk));
         } else if (kind == BK_MFMA) {
             (k == 3 ? n3m : k == 4 ? n4 : n5)++;
             flops += 8.0 * (1 << k);
@@ -63,6 +66,7 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
     f[13] = (float)(ps.nblocks > 0 ? std::log2(1.0 + flops / ps.nblocks) / 10.0 : 0.0);
     f[14] = staged ? 1.0f : 0.0f;
     f[15] = n3m / 8.0f;
+    f[16] = nbd / 8.0f;
 }
 
 namespace {

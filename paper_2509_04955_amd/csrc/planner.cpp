@@ -139,23 +139,58 @@ void block_matrix(const std::vector<HGate> &gates, HBlock &b) {
     }
 }
 
-void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, int c,
-                 std::vector<HPass> &out) {
+// Passes: list scheduling of the blocks over their dependence order (Section
+// 3.4: blocks sharing a qubit keep their order).  A pass starts from the first
+// pending block and its tile {0..c-1}; pending blocks are scanned in order and
+// a block joins the pass if its qubits fit the tile (at most t qubits).  A block
+// that does not fit is left for a later pass and its qubits are marked: no
+// later block touching them may run ahead of it, but blocks on other qubits may
+// still join.  The scan stops kLookahead blocks after the first one left out.
+// The blocks are reordered into execution order (pass by pass), so a pass is a
+// contiguous range; any order produced this way keeps every pair of blocks that
+// share a qubit in program order, hence the same state in exact arithmetic.
+constexpr size_t kLookahead = 64;
+
+void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, std::vector<HPass> &out) {
     out.clear();
     const int n = p.n;
     t = std::min(t, n);
     c = std::min(c, t);
     const uint64_t low = c >= 64 ? ~0ull : ((1ull << c) - 1);
-    uint64_t cur = low;
-    HPass ps;
-    ps.block0 = 0;
-    auto close = [&](int64_t end) {
-        ps.nblocks = end - ps.block0;
+    std::vector<uint64_t> bm(blocks.size(), 0);
+    for (size_t b = 0; b < blocks.size(); ++b)
+        for (int q : blocks[b].qubits) bm[b] |= 1ull << q;
+    std::vector<size_t> pending(blocks.size()), rest;
+    for (size_t b = 0; b < blocks.size(); ++b) pending[b] = b;
+    std::vector<HBlock> ordered;
+    ordered.reserve(blocks.size());
+    while (!pending.empty()) {
+        HPass ps;
+        ps.block0 = (int64_t)ordered.size();
+        uint64_t cur = low, blocked = 0;
+        size_t scanned_after_skip = 0, i = 0;
+        bool skipped = false;
+        rest.clear();
+        for (; i < pending.size(); ++i) {
+            if (skipped && scanned_after_skip++ >= kLookahead) break;
+            const size_t b = pending[i];
+            if ((bm[b] & blocked) == 0 && __builtin_popcountll(cur | bm[b]) <= t) {
+                cur |= bm[b];
+                ordered.push_back(std::move(blocks[b]));
+            } else {
+                blocked |= bm[b];
+                rest.push_back(b);
+                skipped = true;
+            }
+        }
+        rest.insert(rest.end(), pending.begin() + (int64_t)i, pending.end());
+        ps.nblocks = (int64_t)ordered.size() - ps.block0;
+        // the first pending block always fits (c is sized for the widest block)
+        if (ps.nblocks == 0) throw std::logic_error("pass packing made no progress");
         // fill the tile up to t qubits with the lowest unused qubits
         uint64_t m = cur;
         for (int q = 0; q < n && __builtin_popcountll(m) < t; ++q) m |= 1ull << q;
         ps.t = t;
-        ps.tile.clear();
         for (int q = 0; q < n; ++q)
             if ((m >> q) & 1) ps.tile.push_back(q);
         int cc = 0;
@@ -163,20 +198,10 @@ void pack_passes(const qs_plan_s &p, const std::vector<HBlock> &blocks, int t, i
         ps.c = cc;
         // the planner sizes c so that every pass holds exactly t qubits and qubit 0
         if ((int)ps.tile.size() != t || cc < 1) throw std::logic_error("pass tile invariant broken");
-        out.push_back(ps);
-    };
-    for (size_t b = 0; b < blocks.size(); ++b) {
-        uint64_t bm = 0;
-        for (int q : blocks[b].qubits) bm |= 1ull << q;
-        if (__builtin_popcountll(cur | bm) > t) {
-            close((int64_t)b);
-            ps = HPass();
-            ps.block0 = (int64_t)b;
-            cur = low;
-        }
-        cur |= bm;
+        out.push_back(std::move(ps));
+        pending.swap(rest);
     }
-    if (!blocks.empty()) close((int64_t)blocks.size());
+    blocks.swap(ordered);
 }
 
 qs_status build_plan(qs_plan_s &p) {

@@ -248,6 +248,58 @@ __device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, co
     for (uint32_t tk = threadIdx.x; tk < tasks; tk += TT) group(tk);
 }
 
+// ---- permuted block-diagonal block ------------------------------------------
+// The block's 2^K rows and columns split into 2^(K-S) classes of 2^S that U
+// maps onto each other: y[rows of class j] = B_j x[columns of class j].  Pool
+// record: 2^K swizzled tile offsets of the columns (class by class), 2^K of the
+// rows, then B_0, B_1, ... (2^S x 2^S complex, row-major).  One lane holds a
+// whole group, so the in-place update only touches its own amplitudes, and
+// every operand is wave-uniform (scalar loads).
+template <int K, int S, typename R>
+__device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
+                                            const R *__restrict__ E) {
+    using A = typename AmpOf<R>::A;
+    constexpr int D = 1 << K, DS = 1 << S, NC = D / DS;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    const R *B = E + 2 * D;
+    const uint32_t G = 1u << (T - K);
+    for (uint32_t g = threadIdx.x; g < G; g += TT) {
+        uint32_t b = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
+        const uint32_t sb = sw(b);
+        A v[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[i] = tile[sb ^ (uint32_t)E[i]];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            // keeps each class's operand loads beside their use (hoisted out of
+            // the group loop they would need 2^(K+S+1) scalar registers)
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int r = 0; r < DS; ++r) {
+                const R *Br = B + 2 * ((j * DS + r) * DS);
+                R yr = 0, yi = 0;
+#pragma unroll
+                for (int c = 0; c < DS; ++c) {
+                    const A x = v[j * DS + c];
+                    const R ur = Br[2 * c], ui = Br[2 * c + 1];
+                    yr = fma(ur, x.x, yr);
+                    yr = fma(-ui, x.y, yr);
+                    yi = fma(ur, x.y, yi);
+                    yi = fma(ui, x.x, yi);
+                }
+                A y;
+                y.x = yr;
+                y.y = yi;
+                tile[sb ^ (uint32_t)E[D + j * DS + r]] = y;
+            }
+        }
+    }
+}
+
 // ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
 // Y = A X with A = [[Ur, -Ui], [Ui, Ur]] (2D x 2D, D = 2^K) and X the 2D x N
 // real view of the tile (rows: Re then Im of the block's 2^K amplitudes;
@@ -571,6 +623,19 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
             else mfma_block<5>(tile, T, bd, U);
             return;
         }
+    }
+    if (kind == BK_BDIAG) {
+        // class widths 1 <= S < K, K = 3, 4
+        const int sub = bd->sub;
+        if (k == 3) {
+            if (sub == 1) bdiag_block<3, 1, R>(tile, T, bd, U);
+            else bdiag_block<3, 2, R>(tile, T, bd, U);
+        } else if (k == 4) {
+            if (sub == 1) bdiag_block<4, 1, R>(tile, T, bd, U);
+            else if (sub == 2) bdiag_block<4, 2, R>(tile, T, bd, U);
+            else bdiag_block<4, 3, R>(tile, T, bd, U);
+        }
+        return;
     }
     if (kind == BK_MONO) {
         switch (k) {

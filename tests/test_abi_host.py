@@ -90,6 +90,36 @@ def test_block_products_match_oracle(Q, oracle, k_max):
         Q.qs_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("k_max,t,c", [(2, 5, 1), (3, 6, 2), (4, 8, 3), (5, 9, 4)])
+def test_pass_packing_reorders_blocks_validly(Q, oracle, k_max, t, c):
+    """With tiles smaller than the register the packer pulls later blocks on
+    other qubits into earlier passes: the blocks are the oracle's greedy
+    blocks as sets, every pair of gates on a shared qubit keeps its order
+    (the DAG edges of Section 3.4), and the blocks in plan order reproduce
+    the circuit."""
+    n = 12
+    circ = qsynth.random_circuit(n, 300, seed=0, max_dense=2)
+    plan, _ = _plan(Q, circ, k_max=k_max, tile_qubits=t, low_qubits=c)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        ref = greedy.greedy_fw(circ.gates, k_max)
+        qls, mats, blocks = [], [], []
+        for b in range(info.n_blocks):
+            qs, U, mem = Q.qs_plan_block(plan, b)
+            qls.append(qs)
+            mats.append(U)
+            blocks.append(mem)
+        assert sorted(map(tuple, blocks)) == sorted(map(tuple, ref))
+        assert blocks != ref, "expected the packer to move blocks at this tile size"
+        greedy.check_order(circ.gates, blocks)
+        psi0 = qsynth.random_state(n, seed=5)
+        want = oracle.run(circ, psi0.copy())
+        got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
+        assert np.max(np.abs(got - want)) < 1e-12
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
 @pytest.mark.parametrize("t,c", [(8, 3), (10, 6), (13, 6)])
 def test_passes_cover_blocks(Q, t, c):
     circ, _ = qsynth.ucc(24, n_exp=40, seed=4)
@@ -199,6 +229,63 @@ def test_pass_features_on_host(Q):
     try:
         f = costmodel.pass_features(plan)
         assert np.sum(f[:, 8] + f[:, 9]) > 0   # k = 4, 5 dense blocks -> MFMA kind
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+def _class_width(U):
+    """log2 of the narrowest packing of U's nonzero pattern into equal
+    classes: connected components of the row/column graph, first fit by
+    decreasing size into 2^s-wide bins."""
+    D = U.shape[0]
+    nz = np.abs(U) > 1e-14
+    comp = list(range(2 * D))
+
+    def find(x):
+        while comp[x] != x:
+            x = comp[x]
+        return x
+
+    for r, col in zip(*np.nonzero(nz)):
+        comp[find(r)] = find(D + col)
+    sizes = {}
+    for r in range(D):
+        sizes[find(r)] = sizes.get(find(r), 0) + 1
+    sizes = sorted(sizes.values(), reverse=True)
+    s = int(np.ceil(np.log2(sizes[0])))
+    while True:
+        bins = [0] * (D >> s)
+        ok = True
+        for z in sizes:
+            j = next((j for j, b in enumerate(bins) if b + z <= 1 << s), None)
+            if j is None:
+                ok = False
+                break
+            bins[j] += z
+        if ok:
+            return s
+        s += 1
+
+
+@pytest.mark.parametrize("k_max", [3, 4, 5])
+def test_block_diagonal_classification(Q, k_max):
+    """The planner marks a 3- or 4-qubit block permuted block-diagonal when
+    its nonzero pattern packs into classes narrower than the block and wider
+    than one (one is the monomial kind)."""
+    from paper_2509_04955_amd import costmodel
+
+    c = qsynth.random_circuit(16, 400, seed=k_max, kinds=["cx", "cz", "rz", "t", "x", "h", "ry"])
+    plan, _ = _plan(Q, c, k_max=k_max, tile_qubits=12)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        want = 0
+        for b in range(info.n_blocks):
+            qs, U, _ = Q.qs_plan_block(plan, b)
+            s = _class_width(U)
+            want += int(len(qs) in (3, 4) and 1 <= s < len(qs))
+        f = costmodel.pass_features(plan)
+        assert want > 0
+        assert round(float(f[:, 16].sum()) * 8) == want
     finally:
         Q.qs_plan_destroy(plan)
 

@@ -202,6 +202,32 @@ def test_fused_monomial_blocks(Q, oracle, dtype, k_max):
     assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("k_max", [3, 4])
+@pytest.mark.parametrize("t", [9, 12, 13])
+def test_fused_block_diagonal_blocks(Q, oracle, dtype, k_max, t):
+    """Permutation and phase gates with a few Hadamards: most fused blocks
+    split into independent 2- or 4-wide classes (permuted block-diagonal)
+    and take the vector-ALU class path; fewer groups than lanes (t = 9) and
+    several groups per lane (t = 13) are both covered."""
+    from paper_2509_04955_amd import costmodel
+
+    n = 14
+    c = qsynth.random_circuit(n, 400, seed=60 + k_max + t,
+                              kinds=["cx", "cx", "cz", "rz", "t", "s", "x", "h"])
+    gl = Q.GateList(c)
+    plan = Q.qs_contract(n, gl, Q.opts(k_max=k_max, tile_qubits=t, dtype=dtype))
+    try:
+        f = costmodel.pass_features(plan)
+        assert f[:, 16].sum() > 0, "no permuted block-diagonal blocks in this plan"
+    finally:
+        Q.qs_plan_destroy(plan)
+    psi0 = qsynth.random_state(n, seed=9)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=k_max, tile_qubits=t)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
 @pytest.mark.parametrize("renorm", [0, 1])
 def test_renorm_chain(Q, oracle, renorm):
     n = 16
