@@ -473,7 +473,7 @@ bool bdiag_split(const std::vector<cd> &U, int k, int &s, std::vector<int> &src,
 }
 
 // Class widths the tile kernel has permuted block-diagonal code for:
-// 1 <= s < k, k = 3 or 4 (a lane holds the whole group: 2^5 amplitudes would
+// 0 <= s < k, k = 3 or 4 (s = 0 is used for 4-qubit monomial blocks only) (a lane holds the whole group: 2^5 amplitudes would
 // not fit beside the prefetched tile); QS_TILE_BDIAG = 0 turns the kind off,
 // a value g > 1 keeps it to s <= k - g.
 int bdiag_gap() {
@@ -488,7 +488,7 @@ int bdiag_gap() {
 bool bdiag_supported(int k, int s, qs_dtype dt) {
     const int gap = bdiag_gap();
     (void)dt;
-    return gap > 0 && k >= 3 && k <= 4 && s >= 1 && s <= k - gap;
+    return gap > 0 && k >= 3 && k <= 4 && s >= 0 && s <= k - gap;
 }
 
 bool staged_enabled() {
@@ -498,6 +498,19 @@ bool staged_enabled() {
         v = e ? atoi(e) != 0 : 1;
     }
     return v == 1;
+}
+
+// A pool entry holding a 32-bit pattern (read back by bit-cast on the device).
+template <typename R>
+R pool_entry(uint32_t bits) {
+    R v;
+    if constexpr (sizeof(R) == 4) {
+        std::memcpy(&v, &bits, 4);
+    } else {
+        const uint64_t b64 = bits;
+        std::memcpy(&v, &b64, 8);
+    }
+    return v;
 }
 
 template <typename R>
@@ -514,14 +527,15 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
         d.kind = BK_BDIAG;
         d.sub = sub;
         d.mat_off = (int32_t)pool.size();
+        // offsets: LDS byte offsets within the tile, stored as bit patterns
         auto deposit = [&](int c) {
             uint32_t o = 0;
             for (int j = 0; j < d.k; ++j)
                 if ((c >> j) & 1) o |= 1u << d.pos[j];
-            return sw(o);
+            return pool_entry<R>(sw(o) * 2 * (uint32_t)sizeof(R));
         };
-        for (int i = 0; i < D; ++i) pool.push_back((R)deposit(src[i]));
-        for (int i = 0; i < D; ++i) pool.push_back((R)deposit(dst[i]));
+        for (int i = 0; i < D; ++i) pool.push_back(deposit(src[i]));
+        for (int i = 0; i < D; ++i) pool.push_back(deposit(dst[i]));
         const int DS = 1 << sub;
         for (int j = 0; j < D / DS; ++j)
             for (int r = 0; r < DS; ++r)
@@ -614,7 +628,11 @@ uint64_t resident_groups(const void *fn, size_t lds) {
 int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds) {
     const int k = (int)b.qubits.size();
     std::vector<int> tmp;
-    if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp)) return BK_MONO;
+    // 4-qubit monomial blocks go through the class path with classes of one
+    // (one lane per group, wave-uniform records); other widths keep the
+    // monomial path
+    if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp))
+        return k == 4 && bdiag_supported(4, 0, dt) ? BK_BDIAG : BK_MONO;
     // permuted block-diagonal: 2^s complex multiply-adds per amplitude on the
     // vector ALU instead of a dense product
     int sub = 0;

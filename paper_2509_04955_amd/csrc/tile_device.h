@@ -248,13 +248,18 @@ __device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, co
     for (uint32_t tk = threadIdx.x; tk < tasks; tk += TT) group(tk);
 }
 
+// A 32-bit pattern stored in an operand pool entry (bit-cast, not converted).
+__device__ __forceinline__ uint32_t pool_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t pool_bits(double v) { return (uint32_t)__double_as_longlong(v); }
+
 // ---- permuted block-diagonal block ------------------------------------------
 // The block's 2^K rows and columns split into 2^(K-S) classes of 2^S that U
 // maps onto each other: y[rows of class j] = B_j x[columns of class j].  Pool
 // record: 2^K swizzled tile offsets of the columns (class by class), 2^K of the
 // rows, then B_0, B_1, ... (2^S x 2^S complex, row-major).  One lane holds a
 // whole group, so the in-place update only touches its own amplitudes, and
-// every operand is wave-uniform (scalar loads).
+// every operand is wave-uniform (scalar loads).  The offsets are byte offsets
+// stored as bit patterns: one XOR per LDS address.
 template <int K, int S, typename R>
 __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                             const R *__restrict__ E) {
@@ -264,15 +269,17 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
 #pragma unroll
     for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
     const R *B = E + 2 * D;
+    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
+    auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
     const uint32_t G = 1u << (T - K);
     for (uint32_t g = threadIdx.x; g < G; g += TT) {
         uint32_t b = g;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-        const uint32_t sb = sw(b);
+        const uint32_t sb = sw(b) * (uint32_t)sizeof(A);
         A v[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) v[i] = tile[sb ^ (uint32_t)E[i]];
+        for (int i = 0; i < D; ++i) v[i] = at(sb ^ pool_bits(E[i]));
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             // keeps each class's operand loads beside their use (hoisted out of
@@ -294,7 +301,7 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
                 A y;
                 y.x = yr;
                 y.y = yi;
-                tile[sb ^ (uint32_t)E[D + j * DS + r]] = y;
+                at(sb ^ pool_bits(E[D + j * DS + r])) = y;
             }
         }
     }
@@ -625,13 +632,14 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
         }
     }
     if (kind == BK_BDIAG) {
-        // class widths 1 <= S < K, K = 3, 4
+        // class widths 1 <= S < K, K = 3, 4; S = 0 for K = 4 monomial blocks
         const int sub = bd->sub;
         if (k == 3) {
             if (sub == 1) bdiag_block<3, 1, R>(tile, T, bd, U);
             else bdiag_block<3, 2, R>(tile, T, bd, U);
         } else if (k == 4) {
-            if (sub == 1) bdiag_block<4, 1, R>(tile, T, bd, U);
+            if (sub == 0) bdiag_block<4, 0, R>(tile, T, bd, U);
+            else if (sub == 1) bdiag_block<4, 1, R>(tile, T, bd, U);
             else if (sub == 2) bdiag_block<4, 2, R>(tile, T, bd, U);
             else bdiag_block<4, 3, R>(tile, T, bd, U);
         }

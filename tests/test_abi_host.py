@@ -271,7 +271,7 @@ def _class_width(U):
 def test_block_diagonal_classification(Q, k_max):
     """The planner marks a 3- or 4-qubit block permuted block-diagonal when
     its nonzero pattern packs into classes narrower than the block and wider
-    than one (one is the monomial kind)."""
+    than one; 4-qubit monomial blocks (classes of one) take the same path."""
     from paper_2509_04955_amd import costmodel
 
     c = qsynth.random_circuit(16, 400, seed=k_max, kinds=["cx", "cz", "rz", "t", "x", "h", "ry"])
@@ -282,7 +282,7 @@ def test_block_diagonal_classification(Q, k_max):
         for b in range(info.n_blocks):
             qs, U, _ = Q.qs_plan_block(plan, b)
             s = _class_width(U)
-            want += int(len(qs) in (3, 4) and 1 <= s < len(qs))
+            want += int(len(qs) in (3, 4) and 1 <= s < len(qs)) + int(len(qs) == 4 and s == 0)
         f = costmodel.pass_features(plan)
         assert want > 0
         assert round(float(f[:, 16].sum()) * 8) == want
