@@ -2,8 +2,8 @@
 // fixed contiguous low qubits per tile for a circuit by running candidate
 // plans on the device and keeping the fastest.
 //
-// Stage 1 crosses k_max in 3..5 with t in {11, 12, 13} (capped by n and by the
-// dtype's LDS limit) at 4 and 6 low qubits; stage 2 tries 3 and 5 low qubits
+// Stage 1 crosses k_max in 3..5 with t in 11..14 (complex64; 11..12 for
+// complex128; capped by n and by the dtype's LDS limit) at 4 and 6 low qubits; stage 2 tries 3 and 5 low qubits
 // for the winning (k_max, t).  Fewer fixed low qubits leave more tile slots to
 // the qubits the gates touch (fewer passes) at the price of shorter coalesced
 // runs per tile segment.  Each candidate's plan runs on a scratch state once
@@ -66,7 +66,7 @@ extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, si
             return QS_OK;
         }
     }
-    const int tcap = dtype == QS_C128 ? 12 : 13;
+    const int tcap = dtype == QS_C128 ? 12 : 14;
     int wmax = 1;
     for (size_t i = 0; i < ng; ++i) wmax = std::max(wmax, (int)gates[i].nq);
     struct Cand {

@@ -601,6 +601,10 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
         // vector ALU in its wide variant (no staged FP64 MFMA there), which the
         // single-state timings of the autotuner do not see: keep them narrow.
         if (dt == QS_C128 && (base.k_max == 0 || base.tile_qubits == 0)) o.k_max = std::min(o.k_max, 3);
+        // The single-state pass kernel runs 2^13- and 2^14-amplitude tiles with
+        // 512 and 1024 threads; the batch kernel has 256, where such tiles hold
+        // a CU to one or two workgroups.  Tuned tiles stay at 2^12 here.
+        if ((base.k_max == 0 || base.tile_qubits == 0) && o.tile_qubits > 12) o.tile_qubits = 12;
         qs_plan p = nullptr;
         qs_status st = qs_contract(n_qubits[i], circuits[i], n_gates[i], &o, &p);
         if (st != QS_OK) {

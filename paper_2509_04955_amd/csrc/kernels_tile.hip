@@ -65,13 +65,14 @@ __device__ __forceinline__ void st_nt(V *p, V v) {
     __builtin_nontemporal_store(v, p);
 }
 
-// Tile index li of 16-byte vector vi = tid + TT*j splits into a per-thread
-// part (tid*APV, below TT*APV) and a per-j part (j*TT*APV); both the global
+// Tile index li of 16-byte vector vi = tid + NT*j (NT threads per workgroup)
+// splits into a per-thread part (tid*APV, below NT*APV) and a per-j part
+// (j*NT*APV); both the global
 // offset map and the LDS swizzle are bitwise, so each address is the per-thread
 // constant combined with a wave-uniform per-j value.
 //
 // NJ > 0 fixes the number of 16-byte vectors per thread at compile time (the
-// tile is exactly NJ*TT*APV amplitudes): every load and store is then
+// tile is exactly NJ*NT*APV amplitudes): every load and store is then
 // unconditional and the next tile's vectors beyond the prefetch depth are
 // loaded into registers after the blocks, before the stores.
 // NJ = 0 handles any tile size; vectors beyond the prefetch depth are then
@@ -83,15 +84,17 @@ __device__ __forceinline__ void st_nt(V *p, V v) {
 // variants take twice the registers and prefetch the whole next tile.
 // With the pass's block operands staged in LDS (CL) a 2^12-amplitude
 // complex64 tile runs 3 workgroups per CU, leaving about 20 KB of LDS per
-// workgroup for the operands.
+// workgroup for the operands.  Unstaged 2^13- and 2^14-amplitude complex64
+// tiles run with 512 and 1024 threads (8 vectors per thread, 4 waves per
+// SIMD): 2 workgroups per CU and 1, the same wave count as 2^12 tiles.
 template <typename R, bool WIDE, int NJ, bool CL>
 constexpr int tile_waves() {
     // NJ = 0 (tiles below 2^9 complex64 amplitudes) never fills a CU anyway
     return WIDE ? 1 : (sizeof(R) == 4 && NJ > 0 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
 }
 
-template <typename R, bool WIDE, int NJ, bool CL>
-__global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pass(
+template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
+__global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pass(
     typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
     const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials) {
     using A = typename AmpOf<R>::A;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
     constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *tile = reinterpret_cast<A *>(smem_raw);
-    __shared__ double red[TT / 64];
+    __shared__ double red[NT / 64];
     const int T = pa.t;
     const uint32_t tsize = 1u << T;
     const R sc = pa.apply_scale ? (R)(*scale_in) : (R)1;
@@ -110,14 +113,14 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
     const bool active = NJ > 0 || my_li < tsize;   // small tiles: fewer vectors than threads
     const uint64_t g_t = active ? tile_offset(my_li, pa) : 0;
     const uint32_t s_t = sw(my_li);
-    const uint32_t nj = NJ > 0 ? (uint32_t)NJ : (tsize + TT * APV - 1) / (TT * APV);   // vectors per thread
+    const uint32_t nj = NJ > 0 ? (uint32_t)NJ : (tsize + NT * APV - 1) / (NT * APV);   // vectors per thread
     using V = typename Vec16<R>::V;
     V pre[PF];
     auto gaddr = [&](uint64_t base, uint32_t j) -> V * {
-        return reinterpret_cast<V *>(psi + (base | g_t | tile_offset(j * TT * APV, pa)));
+        return reinterpret_cast<V *>(psi + (base | g_t | tile_offset(j * NT * APV, pa)));
     };
     auto lds_put = [&](uint32_t j, V v) {
-        const uint32_t si = s_t ^ sw(j * TT * APV);
+        const uint32_t si = s_t ^ sw(j * NT * APV);
         *reinterpret_cast<V *>(tile + si) = v * sc;
     };
     // Vectors of a generic tile beyond the prefetch depth: loaded in batches
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
     R *cst = reinterpret_cast<R *>(smem_raw + (size_t)tsize * sizeof(A));
     if constexpr (CL) {
         constexpr int EPV = 16 / sizeof(R);
-        for (int i = threadIdx.x * EPV; i < pa.cl_len; i += TT * EPV)
+        for (int i = threadIdx.x * EPV; i < pa.cl_len; i += NT * EPV)
             *reinterpret_cast<V *>(cst + i) = *reinterpret_cast<const V *>(pool + pa.cl_off + i);
     }
     uint64_t base = tile_base(tileid, pa);
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
         }
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
-            apply_block<R, WIDE, CL>(tile, T, blocks + pa.block0 + b, pool, cst, pa.cl_off);
+            apply_block<R, WIDE, CL, NT>(tile, T, blocks + pa.block0 + b, pool, cst, pa.cl_off);
             __syncthreads();
         }
         V ex[EX > 0 ? EX : 1];
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
         double nacc = 0.0;
         if (active) {
             for (uint32_t j = 0; j < nj; ++j) {
-                const V v = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * TT * APV)));
+                const V v = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * NT * APV)));
                 st_nt(gaddr(base, j), v);
                 if constexpr (F32) {
                     nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(TT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pa
             if (threadIdx.x == 0) {
                 double s = 0;
 #pragma unroll
-                for (int w = 0; w < TT / 64; ++w) s += red[w];
+                for (int w = 0; w < NT / 64; ++w) s += red[w];
                 wg_norm += s;
             }
         }
@@ -272,6 +275,17 @@ __global__ __launch_bounds__(256) void k_norm_parts(const A *__restrict__ psi, u
     if (threadIdx.x == 0) parts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// 2^13 / 2^14-amplitude complex64 tiles in 512 / 1024-thread workgroups
+// (QS_TILE_BIG=0: 256 threads)
+bool big_tiles_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_TILE_BIG");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v == 1;
+}
+
 template <typename R>
 using TileKernel = void (*)(typename AmpOf<R>::A *, uint64_t, PassArgs, const BlockDev *, const R *, const double *,
                             double *);
@@ -279,10 +293,24 @@ using TileKernel = void (*)(typename AmpOf<R>::A *, uint64_t, PassArgs, const Bl
 // Kernel variant for a pass: register footprint (wide), LDS-staged operands
 // (cl) and, for the narrow variant, the compile-time vector count.
 template <typename R>
-TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl) {
+TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
     constexpr int APV = sizeof(R) == 4 ? 2 : 1;
     const int vpt = (1 << t) / (TT * APV);   // 16-byte vectors per thread
+    threads = TT;
     if (wide) return k_tile_pass<R, true, 0, false>;
+    if constexpr (sizeof(R) == 4) {
+        // unstaged 2^13 / 2^14 tiles: more threads per workgroup, 8 vectors each
+        if (!cl && big_tiles_enabled()) {
+            if (t == 13) {
+                threads = 512;
+                return k_tile_pass<R, false, 8, false, 512>;
+            }
+            if (t == 14) {
+                threads = 1024;
+                return k_tile_pass<R, false, 8, false, 1024>;
+            }
+        }
+    }
     if ((1 << t) == vpt * TT * APV) {
         if (cl) {
             if constexpr (sizeof(R) == 4) {
@@ -311,7 +339,10 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl) {
 size_t lds_operand_budget(int t, qs_dtype dt) {
     constexpr size_t kLds = 160 * 1024, kMargin = 512;
     int wgs = 0;
-    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : 0;
+    // complex64 2^13 tiles run unstaged in 512-thread workgroups (a staged
+    // 512-thread variant would spill at 4 waves per SIMD); the 256-thread
+    // staged variant is kept for QS_TILE_BIG=0
+    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 && !big_tiles_enabled() ? 2 : 0;
     else wgs = t == 11 || t == 12 ? 2 : 0;   // complex128 variants run 2 workgroups per CU
     if (!wgs) return 0;
     const size_t share = (kLds / wgs) & ~(size_t)1023, tile = (size_t)(dt == QS_C64 ? 8 : 16) << t;
@@ -607,7 +638,7 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
 }
 
 // Workgroups of a tile kernel resident at once on the current device.
-uint64_t resident_groups(const void *fn, size_t lds) {
+uint64_t resident_groups(const void *fn, int threads, size_t lds) {
     static int cus = 0;
     if (!cus) {
         int dev = 0;
@@ -618,7 +649,7 @@ uint64_t resident_groups(const void *fn, size_t lds) {
     }
     int per_cu = 0;
     set_lds_limit(fn, lds);
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TT, lds);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return (uint64_t)per_cu * (uint64_t)cus;
 }
@@ -752,9 +783,13 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     const bool wide = p.pass_wide[di][pass_index] != 0;
     const size_t amp = s.dtype == QS_C64 ? 8 : 16;
     const size_t lds = (amp << ps.t) + (size_t)pa.cl_len * (s.dtype == QS_C64 ? 4 : 8);
-    const void *fn = s.dtype == QS_C64 ? reinterpret_cast<const void *>(pick_tile_kernel<float>(wide, ps.t, cl))
-                                       : reinterpret_cast<const void *>(pick_tile_kernel<double>(wide, ps.t, cl));
-    const uint64_t resident = resident_groups(fn, lds);
+    int threads = TT;
+    TileKernel<float> k32 = nullptr;
+    TileKernel<double> k64 = nullptr;
+    if (s.dtype == QS_C64) k32 = pick_tile_kernel<float>(wide, ps.t, cl, threads);
+    else k64 = pick_tile_kernel<double>(wide, ps.t, cl, threads);
+    const void *fn = k32 ? reinterpret_cast<const void *>(k32) : reinterpret_cast<const void *>(k64);
+    const uint64_t resident = resident_groups(fn, threads, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
     if (want_norm) {
         qs_status st = ensure_partials(s, grid.x);
@@ -767,10 +802,10 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
         flops += block_flops_per_amp(p.h_blocks[di][b]) * std::ldexp(1.0, s.n);
     prof_begin(s.stream, QS_PROF_TILE, 2 * S, flops);
     if (s.dtype == QS_C64)
-        hipLaunchKernelGGL(pick_tile_kernel<float>(wide, ps.t, cl), grid, dim3(TT), lds, s.stream, (float2 *)s.amp, ntiles,
+        hipLaunchKernelGGL(k32, grid, dim3(threads), lds, s.stream, (float2 *)s.amp, ntiles,
                            pa, p.d_blocks[di], (const float *)p.d_pool[di], s.d_slots + 1, s.d_partials);
     else
-        hipLaunchKernelGGL(pick_tile_kernel<double>(wide, ps.t, cl), grid, dim3(TT), lds, s.stream, (double2 *)s.amp,
+        hipLaunchKernelGGL(k64, grid, dim3(threads), lds, s.stream, (double2 *)s.amp,
                            ntiles, pa, p.d_blocks[di], (const double *)p.d_pool[di], s.d_slots + 1, s.d_partials);
     prof_end(s.stream);
     QS_HIP(hipGetLastError());

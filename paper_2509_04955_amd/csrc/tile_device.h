@@ -123,7 +123,7 @@ __device__ __forceinline__ void dense_group(typename AmpOf<R>::A *tile, uint32_t
     }
 }
 
-template <int K, typename R>
+template <int K, typename R, int NT = TT>
 __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                            const R *__restrict__ U) {
     using A = typename AmpOf<R>::A;
@@ -148,10 +148,10 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
         return sw(b);
     };
     if constexpr (K <= 3) {
-        if (G >= 2 * TT) {
+        if (G >= 2 * NT) {
             // G is a power of two >= 512: every lane has exactly G / 512 pairs of groups
-            for (uint32_t g = threadIdx.x; g < G; g += 2 * TT) {
-                const uint32_t b0 = base_of(g), b1 = base_of(g + TT);
+            for (uint32_t g = threadIdx.x; g < G; g += 2 * NT) {
+                const uint32_t b0 = base_of(g), b1 = base_of(g + NT);
                 A v0[D], v1[D];
 #pragma unroll
                 for (int r = 0; r < D; ++r) {
@@ -185,7 +185,7 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
             return;
         }
     }
-    for (uint32_t g = threadIdx.x; g < G; g += TT) dense_group<K, R>(tile, base_of(g), off, U);
+    for (uint32_t g = threadIdx.x; g < G; g += NT) dense_group<K, R>(tile, base_of(g), off, U);
 }
 
 // ---- monomial block: one nonzero per column ---------------------------------
@@ -195,7 +195,7 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
 // one wave (LPG = 1 for K <= 3, 2^(K-3) above), each holding 8 or fewer
 // sources; the lanes of a wave issue all their LDS reads before any write, so
 // the in-place permutation is safe.
-template <int K, typename R>
+template <int K, typename R, int NT = TT>
 __device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                            const R *__restrict__ E) {
     using A = typename AmpOf<R>::A;
@@ -237,15 +237,15 @@ __device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, co
         }
     };
     if constexpr (K <= 3) {
-        if (tasks >= 2 * TT) {
-            for (uint32_t tk = threadIdx.x; tk < tasks; tk += 2 * TT) {
+        if (tasks >= 2 * NT) {
+            for (uint32_t tk = threadIdx.x; tk < tasks; tk += 2 * NT) {
                 group(tk);
-                group(tk + TT);
+                group(tk + NT);
             }
             return;
         }
     }
-    for (uint32_t tk = threadIdx.x; tk < tasks; tk += TT) group(tk);
+    for (uint32_t tk = threadIdx.x; tk < tasks; tk += NT) group(tk);
 }
 
 // A 32-bit pattern stored in an operand pool entry (bit-cast, not converted).
@@ -260,7 +260,7 @@ __device__ __forceinline__ uint32_t pool_bits(double v) { return (uint32_t)__dou
 // whole group, so the in-place update only touches its own amplitudes, and
 // every operand is wave-uniform (scalar loads).  The offsets are byte offsets
 // stored as bit patterns: one XOR per LDS address.
-template <int K, int S, typename R>
+template <int K, int S, typename R, int NT = TT>
 __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                             const R *__restrict__ E) {
     using A = typename AmpOf<R>::A;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
     unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
     auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
     const uint32_t G = 1u << (T - K);
-    for (uint32_t g = threadIdx.x; g < G; g += TT) {
+    for (uint32_t g = threadIdx.x; g < G; g += NT) {
         uint32_t b = g;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
@@ -318,13 +318,13 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
 // K = 5 has 4 M-tiles, one per wave; K = 4 has 2, and the waves sharing one
 // split the columns.  Columns go in rounds of 4 chunks of 16 per wave: all
 // waves read their inputs, a barrier, then all write (in place).
-template <int K>
+template <int K, int NT = TT>
 __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *bd, const float *__restrict__ Asw) {
     constexpr int D = 1 << K;
     constexpr int MT = 2 * D / 16;
     constexpr int S = 2 * D / 4;
     constexpr int NB = D / 4;
-    constexpr int CPW = 4 / MT;   // waves per M-tile
+    constexpr int CPW = (NT / 64) / MT;   // waves per M-tile
     constexpr int CR = 4;         // chunks per wave per round
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -404,7 +404,7 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
 // amplitude R mod 2^K, real part when R < 2^K (K = 3 has one M-tile holding
 // both parts); for FP64 the row of item q is 16 m + lane/16 + 4q.  CPI chunks are in flight per wave (CPI * MT accumulator
 // chains).
-template <int K, typename R>
+template <int K, typename R, int NT = TT>
 __device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T, const BlockDev *bd, const R *As) {
     using A = typename AmpOf<R>::A;
     using V4 = typename Mfma<R>::V4;
@@ -442,7 +442,7 @@ __device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T
     R *tf = reinterpret_cast<R *>(tile);
     const V4 *A4 = reinterpret_cast<const V4 *>(As);
     const uint32_t nchunks = (1u << (T - K)) / 16;
-    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += 4 * CPI) {
+    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += (NT / 64) * CPI) {
         uint32_t cb[CPI];
         A bv[CPI][NB];
 #pragma unroll
@@ -499,7 +499,7 @@ __device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T
 // in LDS: [g = Ur, Ui, Ur+Ui][M-tile][s/4][lane][s%4].  As in mfma_block_lds
 // each wave owns whole chunks: no barrier inside the block.  K = 4 keeps all
 // of A in registers for the block; K = 5 re-reads it per chunk.
-template <int K, typename R>
+template <int K, typename R, int NT = TT>
 __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int T, const BlockDev *bd, const R *As) {
     using A = typename AmpOf<R>::A;
     using V4 = typename Mfma<R>::V4;
@@ -543,7 +543,7 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
                 for (int s4 = 0; s4 < S4; ++s4) ah[(g * MT + m) * S4 + s4] = A4[aidx(g, m, s4)];
     }
     const uint32_t nchunks = (1u << (T - K)) / 16;
-    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += 4 * CPI) {
+    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += (NT / 64) * CPI) {
         uint32_t cb[CPI];
         A bv[CPI][S];
 #pragma unroll
@@ -611,7 +611,7 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
 // three-product form; FP32 or FP64 matrix cores) and monomial
 // blocks with k >= 4 (per-lane records) read them there, dense VALU blocks and
 // narrow monomial blocks keep their wave-uniform scalar loads from the pool.
-template <typename R, bool WIDE, bool CL = false>
+template <typename R, bool WIDE, bool CL = false, int NT = TT>
 __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                             const R *__restrict__ pool, const R *cst = nullptr, int cl_off = 0) {
     const int k = bd->k;
@@ -621,13 +621,13 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     if (kind == BK_MFMA) {
         if constexpr (CL) {
             const R *As = cst + (bd->mat_off - cl_off);
-            if (k == 3) mfma_block_lds<3, R>(tile, T, bd, As);
-            else if (k == 4) mfma3m_block_lds<4, R>(tile, T, bd, As);
-            else mfma3m_block_lds<5, R>(tile, T, bd, As);
+            if (k == 3) mfma_block_lds<3, R, NT>(tile, T, bd, As);
+            else if (k == 4) mfma3m_block_lds<4, R, NT>(tile, T, bd, As);
+            else mfma3m_block_lds<5, R, NT>(tile, T, bd, As);
             return;
         } else if constexpr (F32) {
-            if (k == 4) mfma_block<4>(tile, T, bd, U);
-            else mfma_block<5>(tile, T, bd, U);
+            if (k == 4) mfma_block<4, NT>(tile, T, bd, U);
+            else mfma_block<5, NT>(tile, T, bd, U);
             return;
         }
     }
@@ -635,49 +635,49 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
         // class widths 1 <= S < K, K = 3, 4; S = 0 for K = 4 monomial blocks
         const int sub = bd->sub;
         if (k == 3) {
-            if (sub == 1) bdiag_block<3, 1, R>(tile, T, bd, U);
-            else bdiag_block<3, 2, R>(tile, T, bd, U);
+            if (sub == 1) bdiag_block<3, 1, R, NT>(tile, T, bd, U);
+            else bdiag_block<3, 2, R, NT>(tile, T, bd, U);
         } else if (k == 4) {
-            if (sub == 0) bdiag_block<4, 0, R>(tile, T, bd, U);
-            else if (sub == 1) bdiag_block<4, 1, R>(tile, T, bd, U);
-            else if (sub == 2) bdiag_block<4, 2, R>(tile, T, bd, U);
-            else bdiag_block<4, 3, R>(tile, T, bd, U);
+            if (sub == 0) bdiag_block<4, 0, R, NT>(tile, T, bd, U);
+            else if (sub == 1) bdiag_block<4, 1, R, NT>(tile, T, bd, U);
+            else if (sub == 2) bdiag_block<4, 2, R, NT>(tile, T, bd, U);
+            else bdiag_block<4, 3, R, NT>(tile, T, bd, U);
         }
         return;
     }
     if (kind == BK_MONO) {
         switch (k) {
-        case 1: mono_block<1, R>(tile, T, bd, U); return;
-        case 2: mono_block<2, R>(tile, T, bd, U); return;
-        case 3: mono_block<3, R>(tile, T, bd, U); return;
+        case 1: mono_block<1, R, NT>(tile, T, bd, U); return;
+        case 2: mono_block<2, R, NT>(tile, T, bd, U); return;
+        case 3: mono_block<3, R, NT>(tile, T, bd, U); return;
         default: break;
         }
         if constexpr (CL) {
             const R *E = cst + (bd->mat_off - cl_off);
             switch (k) {
-            case 4: mono_block<4, R>(tile, T, bd, E); return;
-            case 5: mono_block<5, R>(tile, T, bd, E); return;
-            default: mono_block<6, R>(tile, T, bd, E); return;
+            case 4: mono_block<4, R, NT>(tile, T, bd, E); return;
+            case 5: mono_block<5, R, NT>(tile, T, bd, E); return;
+            default: mono_block<6, R, NT>(tile, T, bd, E); return;
             }
         } else {
             switch (k) {
-            case 4: mono_block<4, R>(tile, T, bd, U); return;
-            case 5: mono_block<5, R>(tile, T, bd, U); return;
-            default: mono_block<6, R>(tile, T, bd, U); return;
+            case 4: mono_block<4, R, NT>(tile, T, bd, U); return;
+            case 5: mono_block<5, R, NT>(tile, T, bd, U); return;
+            default: mono_block<6, R, NT>(tile, T, bd, U); return;
             }
         }
     }
     switch (k) {
-    case 1: valu_block<1, R>(tile, T, bd, U); return;
-    case 2: valu_block<2, R>(tile, T, bd, U); return;
-    case 3: valu_block<3, R>(tile, T, bd, U); return;
+    case 1: valu_block<1, R, NT>(tile, T, bd, U); return;
+    case 2: valu_block<2, R, NT>(tile, T, bd, U); return;
+    case 3: valu_block<3, R, NT>(tile, T, bd, U); return;
     default: break;
     }
     if constexpr (WIDE) {
-        if (k == 4) valu_block<4, R>(tile, T, bd, U);
-        else if (k == 5) valu_block<5, R>(tile, T, bd, U);
+        if (k == 4) valu_block<4, R, NT>(tile, T, bd, U);
+        else if (k == 5) valu_block<5, R, NT>(tile, T, bd, U);
         if constexpr (F32) {
-            if (k == 6) valu_block<6, R>(tile, T, bd, U);
+            if (k == 6) valu_block<6, R, NT>(tile, T, bd, U);
         }
     }
 }

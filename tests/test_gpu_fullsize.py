@@ -128,3 +128,29 @@ def test_ucc_prefix_and_inverse_return_to_zero_30q(Q):
     a0 = amps_at(Q, s, [0])[0]
     assert 1 - abs(a0) ** 2 <= 1e-5
     s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("t", [13, 14])
+def test_large_tiles_30q(Q, t):
+    """2^13- and 2^14-amplitude tiles (512- and 1024-thread workgroups, several
+    tiles per workgroup at 30 qubits): the UCC prefix's nonzero amplitudes
+    against the closed form, and sampled QFT amplitudes with dense 4- and
+    5-qubit blocks."""
+    c, rots = qsynth.ucc(N, n_exp=10, seed=3)
+    s = run(Q, c, 0, k_max=4, tile_qubits=t, low_qubits=4)
+    exact = sparse_rotations(rots)
+    idx = sorted(exact)
+    got = amps_at(Q, s, idx)
+    assert np.max(np.abs(got - np.array([exact[k] for k in idx]))) <= 1e-5
+    assert abs(s.norm() - 1.0) <= 1e-4
+    s.close()
+    x = 0x1F00D5
+    s = run(Q, qsynth.qft(N), 0, basis=x, k_max=5, tile_qubits=t, low_qubits=4)
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([[0, 1, (1 << N) - 1], rng.integers(0, 1 << N, size=253)])
+    got = amps_at(Q, s, idx)
+    ang = 2 * np.pi * ((x * idx.astype(object)) % (1 << N)).astype(np.float64) / (1 << N)
+    ref = np.exp(1j * ang) / math.sqrt(1 << N)
+    assert np.max(np.abs(got - ref)) <= 1e-5 / math.sqrt(1 << N) * 30
+    s.close()
