@@ -87,20 +87,21 @@ __device__ __forceinline__ void st_nt(V *p, V v) {
 // workgroup for the operands.  Unstaged 2^13- and 2^14-amplitude complex64
 // tiles run with 512 and 1024 threads (8 vectors per thread, 4 waves per
 // SIMD): 2 workgroups per CU and 1, the same wave count as 2^12 tiles.
-template <typename R, bool WIDE, int NJ, bool CL>
+template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
 constexpr int tile_waves() {
     // NJ = 0 (tiles below 2^9 complex64 amplitudes) never fills a CU anyway
+    if (NT > TT) return 4;
     return WIDE ? 1 : (sizeof(R) == 4 && NJ > 0 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
 }
 
 template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
-__global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL>())) void k_tile_pass(
+__global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_tile_pass(
     typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
     const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials) {
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
-    constexpr int PFMAX = tile_waves<R, WIDE, NJ, CL>() <= 3 ? (sizeof(R) == 8 ? 8 : 16) : kPrefetch;
+    constexpr int PFMAX = NT > TT && CL ? 4 : tile_waves<R, WIDE, NJ, CL, NT>() <= 3 ? (sizeof(R) == 8 ? 8 : 16) : kPrefetch;
     constexpr int PF = NJ > 0 ? (NJ < PFMAX ? NJ : PFMAX) : kPrefetch;
     constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -310,6 +311,14 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
                 return k_tile_pass<R, false, 8, false, 1024>;
             }
         }
+        if (cl && big_tiles_enabled() && t == 13) {
+            threads = 512;
+            return k_tile_pass<R, false, 8, true, 512>;
+        }
+        if (cl && big_tiles_enabled() && t == 14) {
+            threads = 1024;
+            return k_tile_pass<R, false, 8, true, 1024>;
+        }
     }
     if ((1 << t) == vpt * TT * APV) {
         if (cl) {
@@ -339,15 +348,18 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
 size_t lds_operand_budget(int t, qs_dtype dt) {
     constexpr size_t kLds = 160 * 1024, kMargin = 512;
     int wgs = 0;
-    // complex64 2^13 tiles run unstaged in 512-thread workgroups (a staged
-    // 512-thread variant would spill at 4 waves per SIMD); the 256-thread
-    // staged variant is kept for QS_TILE_BIG=0
-    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 && !big_tiles_enabled() ? 2 : 0;
+    // complex64 2^13 / 2^14 tiles: 2 / 1 workgroups per CU (512 / 1024 threads,
+    // or 2 of 256 threads for 2^13 with QS_TILE_BIG=0)
+    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : t == 14 && big_tiles_enabled() ? 1 : 0;
     else wgs = t == 11 || t == 12 ? 2 : 0;   // complex128 variants run 2 workgroups per CU
     if (!wgs) return 0;
     const size_t share = (kLds / wgs) & ~(size_t)1023, tile = (size_t)(dt == QS_C64 ? 8 : 16) << t;
     return share > tile + kMargin ? share - tile - kMargin : 0;
 }
+
+// Staged complex64 passes in 512 / 1024-thread workgroups apply 5-qubit
+// blocks with the real embedding (the three-product form would spill there).
+bool big_staged(int t, qs_dtype dt) { return dt == QS_C64 && (t == 13 || t == 14) && big_tiles_enabled(); }
 
 // Raise a kernel's dynamic LDS limit once per (kernel, size).
 void set_lds_limit(const void *fn, size_t bytes) {
@@ -591,7 +603,7 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
     } else if (kind == BK_MFMA) {
         d.kind = BK_MFMA;
         d.mat_off = (int32_t)pool.size();
-        if (lds && d.k >= 4) swizzle_mfma3m<R>(blk.U, d.k, pool);
+        if (lds && d.k >= 4 && !(d.k == 5 && big_staged(t, dt))) swizzle_mfma3m<R>(blk.U, d.k, pool);
         else swizzle_mfma<R>(blk.U, d.k, lds, pool);
     } else {
         d.kind = BK_DENSE;
@@ -628,7 +640,8 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
         size_t e = kind == BK_MONO    ? 4 * (size_t)D
-                   : kind == BK_MFMA  ? (k >= 4 ? (size_t)3 * D * D : (size_t)4 * D * D)
+                   : kind == BK_MFMA  ? (k == 4 || (k == 5 && !big_staged(ps.t, dt)) ? (size_t)3 * D * D
+                                                                                      : (size_t)4 * D * D)
                    : kind == BK_BDIAG ? 2 * (size_t)D + 2 * (size_t)D * bdiag_width(blk)
                                       : 2 * (size_t)D * D;
         e = (e + 3) / 4 * 4;

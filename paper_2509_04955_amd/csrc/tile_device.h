@@ -623,6 +623,7 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
             const R *As = cst + (bd->mat_off - cl_off);
             if (k == 3) mfma_block_lds<3, R, NT>(tile, T, bd, As);
             else if (k == 4) mfma3m_block_lds<4, R, NT>(tile, T, bd, As);
+            else if constexpr (NT > TT) mfma_block_lds<5, R, NT>(tile, T, bd, As);
             else mfma3m_block_lds<5, R, NT>(tile, T, bd, As);
             return;
         } else if constexpr (F32) {

@@ -147,12 +147,13 @@ def test_fused_low_qubit_counts(Q, oracle, dtype, low, t):
 
 
 @pytest.mark.parametrize("n5,n3", [(1, 2), (0, 6), (3, 0), (2, 3)])
-@pytest.mark.parametrize("t", [11, 12, 13])
+@pytest.mark.parametrize("t", [11, 12, 13, 14])
 def test_fused_mfma_operands_staged_or_not(Q, oracle, n5, n3, t):
-    """Passes whose MFMA operands fit the LDS left beside the tile (one dense
-    5-qubit block = 16 KB, 3-qubit blocks 1 KB each) stage them there and also
-    run 3-qubit blocks on MFMA; passes over the budget (several 5-qubit
-    blocks) read them from the pool.  Both give the oracle's state."""
+    """Passes whose MFMA operands fit the LDS left beside the tile (a dense
+    5-qubit block is 12 KB in the three-product form, 16 KB embedded as in
+    the 512/1024-thread workgroups of 2^13/2^14 tiles; 3-qubit blocks 1 KB)
+    stage them there and also run 3-qubit blocks on MFMA; passes over the
+    budget read them from the pool.  Both give the oracle's state."""
     n = 15
     rng = np.random.default_rng(100 * n5 + n3 + t)
 
