@@ -229,6 +229,19 @@ def test_fused_block_diagonal_blocks(Q, oracle, dtype, k_max, t):
     assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("n", [4, 5, 7])
+def test_fused_block_diagonal_small_states(Q, oracle, dtype, n):
+    """Class-path blocks when the tile is the whole state and a workgroup has
+    fewer groups than lanes (down to one group)."""
+    c = qsynth.random_circuit(n, 120, seed=70 + n, kinds=["cx", "cz", "rz", "t", "x", "h"])
+    psi0 = qsynth.random_state(n, seed=12)
+    ref = oracle.run(c, psi0.copy())
+    for k_max in (3, 4):
+        got, _ = run_plan(Q, c, dtype, psi0, k_max=min(k_max, n), tile_qubits=n)
+        assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
 @pytest.mark.parametrize("renorm", [0, 1])
 def test_renorm_chain(Q, oracle, renorm):
     n = 16
