@@ -151,6 +151,9 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
         if (G >= 2 * NT) {
             // G is a power of two >= 512: every lane has exactly G / 512 pairs of groups
             for (uint32_t g = threadIdx.x; g < G; g += 2 * NT) {
+                // matrix loads stay in the loop: hoisted, the 2^(2K+1) scalar
+                // values would be spilled and re-read lane by lane every iteration
+                asm volatile("" ::: "memory");
                 const uint32_t b0 = base_of(g), b1 = base_of(g + NT);
                 A v0[D], v1[D];
 #pragma unroll
@@ -185,7 +188,10 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
             return;
         }
     }
-    for (uint32_t g = threadIdx.x; g < G; g += NT) dense_group<K, R>(tile, base_of(g), off, U);
+    for (uint32_t g = threadIdx.x; g < G; g += NT) {
+        asm volatile("" ::: "memory");
+        dense_group<K, R>(tile, base_of(g), off, U);
+    }
 }
 
 // ---- monomial block: one nonzero per column ---------------------------------
