@@ -80,7 +80,11 @@ typedef struct qs_batch_s *qs_batch;
 enum {
     QS_STRATEGY_NONE = 0,    /* one block per gate, still streamed in tile passes */
     QS_STRATEGY_GREEDY = 1,  /* fixed-width greedy merge over the DAG (width k_max) */
-    QS_STRATEGY_LEARNED = 2  /* widths chosen per pass by the loaded cost model; greedy if none loaded */
+    QS_STRATEGY_LEARNED = 2, /* widths chosen per pass by the loaded cost model; greedy if none loaded */
+    QS_STRATEGY_PAULI = 3    /* greedy, after contracting every run of gates that multiplies to one
+                                Pauli rotation exp(-i phi P) (Clifford gates around one diagonal
+                                one-qubit gate, Clifford parts cancelling, X support <= 8 qubits
+                                and < tile_qubits) into one block; beyond Section 3.4's rule */
 };
 
 typedef struct {
@@ -151,8 +155,10 @@ qs_status qs_plan_destroy(qs_plan p);
 qs_status qs_plan_info_get(qs_plan p, qs_plan_info *info);
 /* Block b: width k, its qubits ascending (k entries), its FP64 matrix
  * (4^k complex, interleaved, row-major, local bit j <-> j-th smallest qubit;
- * NULL to skip), and its member gate indices in program order (member_cap
- * entries at most; *n_members gets the true count). */
+ * NULL to skip; QS_EUNSUPPORTED for Pauli-rotation blocks wider than 10
+ * qubits), and its member gate indices in program order (member_cap entries
+ * at most; *n_members gets the true count).  k may exceed k_max for blocks of
+ * the Pauli strategy (up to 8 + the Z part of the rotation). */
 qs_status qs_plan_block(qs_plan p, uint64_t b, int *k, int *qubits, double *matrix,
                         uint64_t *members, uint64_t member_cap, uint64_t *n_members);
 /* Pass i: tile width t, its tile qubits ascending (t entries), first block

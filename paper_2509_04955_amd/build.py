@@ -23,6 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = [
     "gates.cpp",
     "planner.cpp",
+    "pauli.cpp",
     "learned.cpp",
     "api.cpp",
     "kernels_plain.hip",

@@ -316,11 +316,20 @@ qs_status qs_plan_block(qs_plan p, uint64_t b, int *k, int *qubits, double *matr
     if (k) *k = kk;
     if (qubits)
         for (int j = 0; j < kk; ++j) qubits[j] = B.qubits[j];
-    if (matrix)
-        for (size_t i = 0; i < B.U.size(); ++i) {
-            matrix[2 * i] = B.U[i].real();
-            matrix[2 * i + 1] = B.U[i].imag();
+    if (matrix) {
+        const std::vector<cd> *U = &B.U;
+        HBlock dense;
+        if (B.pauli) {   // Pauli blocks keep (x, z, c, d); the dense form is built on request
+            QS_CHECK(kk <= 10, QS_EUNSUPPORTED, "dense matrix of a %d-qubit Pauli block not available", kk);
+            dense = B;
+            pauli_block_matrix(dense);
+            U = &dense.U;
         }
+        for (size_t i = 0; i < U->size(); ++i) {
+            matrix[2 * i] = (*U)[i].real();
+            matrix[2 * i + 1] = (*U)[i].imag();
+        }
+    }
     if (members)
         for (uint64_t i = 0; i < std::min<uint64_t>(member_cap, B.members.size()); ++i) members[i] = B.members[i];
     if (n_members) *n_members = B.members.size();

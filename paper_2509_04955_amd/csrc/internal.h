@@ -49,6 +49,7 @@ enum : int32_t {
     BK_MFMA = 1,    // complex64, k = 4 or 5: MFMA with a pre-swizzled A operand
     BK_MONO = 2,    // monomial (one nonzero per column): y[dest(c)] = u_c x[c]
     BK_BDIAG = 3,   // permuted block-diagonal: classes of 2^sub rows/columns
+    BK_PAULI = 4,   // Pauli rotation: y[k] = c psi[k] + d sigma(k^x) psi[k^x]
 };
 
 struct BlockDev {
@@ -106,7 +107,20 @@ struct HGate {
 struct HBlock {
     std::vector<int> qubits;     // ascending
     std::vector<int64_t> members;
-    std::vector<cd> U;           // 2^k x 2^k, local bit j <-> qubits[j]
+    std::vector<cd> U;           // 2^k x 2^k, local bit j <-> qubits[j] (empty for Pauli blocks)
+    // Pauli-rotation block (a contracted window, see pauli.cpp): global X and
+    // Z masks and the coefficients of y[k] = c psi[k] + d sigma(k^x) psi[k^x]
+    bool pauli = false;
+    uint64_t px = 0, pz = 0;
+    cd pc, pd;
+};
+
+// A run of gates [begin, end) equal to one Pauli rotation (pauli.cpp).
+struct PauliWindow {
+    int64_t begin = 0, end = 0;
+    uint64_t x = 0, z = 0;
+    std::vector<int> support;    // ascending qubits the run touches
+    cd c, d;
 };
 
 struct HPass {
@@ -156,7 +170,14 @@ bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt
 // packs blocks into passes and reorders them into execution order (in place)
 void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c,
                  std::vector<HPass> &out);
-void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks);
+// solo (optional): units that always form a block of their own
+void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks,
+                   const std::vector<char> *solo = nullptr);
+// pauli.cpp: windows of Clifford gates around one diagonal one-qubit gate whose
+// Clifford parts cancel (X weight at most max_x_weight); dense matrix of a
+// Pauli block on its support
+std::vector<PauliWindow> find_pauli_windows(const std::vector<HGate> &gates, int max_x_weight);
+void pauli_block_matrix(HBlock &b);
 int default_tile(qs_dtype dt);
 // learned.cpp: features of one pass (kNumFeatures floats) and the learned
 // per-window partition

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
         }
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
-            apply_block<R, WIDE, CL, NT>(tile, T, blocks + pa.block0 + b, pool, cst, pa.cl_off);
+            apply_block<R, WIDE, CL, NT>(tile, T, blocks + pa.block0 + b, pool, base, cst, pa.cl_off);
             __syncthreads();
         }
         V ex[EX > 0 ? EX : 1];
@@ -543,6 +543,11 @@ bool staged_enabled() {
     return v == 1;
 }
 
+// Pauli-rotation record: X and Z masks over tile positions, the Z mask of the
+// qubits outside the tile (64-bit, two entries), then c and d.
+template <typename R>
+void push_pauli(const HBlock &blk, BlockDev &d, const HPass &ps, std::vector<R> &pool);
+
 // A pool entry holding a 32-bit pattern (read back by bit-cast on the device).
 template <typename R>
 R pool_entry(uint32_t bits) {
@@ -554,6 +559,31 @@ R pool_entry(uint32_t bits) {
         std::memcpy(&v, &b64, 8);
     }
     return v;
+}
+
+template <typename R>
+void push_pauli(const HBlock &blk, BlockDev &d, const HPass &ps, std::vector<R> &pool) {
+    uint32_t xt = 0, zt = 0;
+    uint64_t tmask = 0;
+    for (size_t j = 0; j < ps.tile.size(); ++j) {
+        const int q = ps.tile[j];
+        tmask |= 1ull << q;
+        if ((blk.px >> q) & 1) xt |= 1u << j;
+        if ((blk.pz >> q) & 1) zt |= 1u << j;
+    }
+    if ((blk.px & ~tmask) != 0) throw std::logic_error("Pauli block's X part outside its tile");
+    const uint64_t zo = blk.pz & ~tmask;
+    d.kind = BK_PAULI;
+    d.k = __builtin_popcount(xt);
+    d.mat_off = (int32_t)pool.size();
+    pool.push_back(pool_entry<R>(xt));
+    pool.push_back(pool_entry<R>(zt));
+    pool.push_back(pool_entry<R>((uint32_t)zo));
+    pool.push_back(pool_entry<R>((uint32_t)(zo >> 32)));
+    pool.push_back((R)blk.pc.real());
+    pool.push_back((R)blk.pc.imag());
+    pool.push_back((R)blk.pd.real());
+    pool.push_back((R)blk.pd.imag());
 }
 
 template <typename R>
@@ -627,6 +657,7 @@ size_t bdiag_width(const HBlock &b) {
 
 // Real flops per amplitude of one block as the tile kernel applies it.
 double block_flops_per_amp(const BlockDev &d) {
+    if (d.kind == BK_PAULI) return 16.0;
     if (d.kind == BK_MONO) return 6.0;
     if (d.kind == BK_BDIAG) return 8.0 * (1 << d.sub);
     return 8.0 * (1 << d.k);
@@ -639,7 +670,8 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
         const HBlock &blk = blocks[i];
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
-        size_t e = kind == BK_MONO    ? 4 * (size_t)D
+        size_t e = kind == BK_PAULI   ? 8
+                   : kind == BK_MONO    ? 4 * (size_t)D
                    : kind == BK_MFMA  ? (k == 4 || (k == 5 && !big_staged(ps.t, dt)) ? (size_t)3 * D * D
                                                                                       : (size_t)4 * D * D)
                    : kind == BK_BDIAG ? 2 * (size_t)D + 2 * (size_t)D * bdiag_width(blk)
@@ -670,6 +702,7 @@ uint64_t resident_groups(const void *fn, int threads, size_t lds) {
 }  // namespace
 
 int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds) {
+    if (b.pauli) return BK_PAULI;
     const int k = (int)b.qubits.size();
     std::vector<int> tmp;
     // 4-qubit monomial blocks go through the class path with classes of one
@@ -733,6 +766,11 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
             const HBlock &blk = p.blocks[b];
             BlockDev &d = hb[b];
             std::memset(&d, 0, sizeof d);
+            if (blk.pauli) {
+                if (dt == QS_C64) push_pauli<float>(blk, d, ps, pool32);
+                else push_pauli<double>(blk, d, ps, pool64);
+                continue;
+            }
             d.k = (int)blk.qubits.size();
             QS_CHECK(d.k >= 1 && d.k <= (dt == QS_C64 ? kMaxK : kMaxK128), QS_EUNSUPPORTED,
                      "block width %d unsupported for this dtype", d.k);

@@ -38,6 +38,9 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
             ++nmono;
             if (k > 4) ++nwide;
             flops += 6;
+        } else if (kind == BK_PAULI) {
+            ++nbd;
+            flops += 16.0;
         } else if (kind == BK_BDIAG) {
             ++nbd;
             flops += 8.0 * (1 << bdiag_log_width(blk));

@@ -57,11 +57,13 @@ struct MinTree {
 
 }  // namespace
 
-void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks) {
+void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks,
+                   const std::vector<char> *solo) {
     blocks.clear();
     std::vector<int> last(n, 0);                 // 1-based block index, 0 = none
     std::vector<uint64_t> qmask;                 // qubit mask per block
     std::vector<int> width;
+    std::vector<char> closed;                    // blocks that take no further gates (solo units)
     MinTree tree(gates.size() + 1);
     for (size_t gi = 0; gi < gates.size(); ++gi) {
         const HGate &g = gates[gi];
@@ -72,9 +74,10 @@ void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector
             f = std::max(f, last[g.q[j]]);
         }
         const int w = g.nq;
+        const bool alone = solo && (*solo)[gi];
         int j = -1;  // 1-based
-        if (w <= kmax) {
-            if (f >= 1 && __builtin_popcountll(qmask[f - 1] | gm) <= kmax) {
+        if (w <= kmax && !alone) {
+            if (f >= 1 && !closed[f - 1] && __builtin_popcountll(qmask[f - 1] | gm) <= kmax) {
                 j = f;
             } else {
                 int idx = tree.first_le(std::max(f + 1, 1), kmax - w);  // tree index = 1-based block id
@@ -85,12 +88,13 @@ void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector
             blocks.emplace_back();
             qmask.push_back(0);
             width.push_back(0);
+            closed.push_back(alone ? 1 : 0);
             j = (int)blocks.size();
         }
         blocks[j - 1].members.push_back((int64_t)gi);
         qmask[j - 1] |= gm;
         width[j - 1] = __builtin_popcountll(qmask[j - 1]);
-        tree.set(j, width[j - 1]);
+        tree.set(j, closed[j - 1] ? 64 : width[j - 1]);
         for (int q = 0; q < g.nq; ++q) last[g.q[q]] = j;
     }
     for (size_t b = 0; b < blocks.size(); ++b) {
@@ -157,9 +161,14 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
     t = std::min(t, n);
     c = std::min(c, t);
     const uint64_t low = c >= 64 ? ~0ull : ((1ull << c) - 1);
-    std::vector<uint64_t> bm(blocks.size(), 0);
-    for (size_t b = 0; b < blocks.size(); ++b)
-        for (int q : blocks[b].qubits) bm[b] |= 1ull << q;
+    // dm: qubits a block depends on (its support); bm: qubits it needs in the
+    // tile (the support, or the X part of a Pauli rotation: its Z part outside
+    // the tile is a per-tile sign)
+    std::vector<uint64_t> bm(blocks.size(), 0), dm(blocks.size(), 0);
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        for (int q : blocks[b].qubits) dm[b] |= 1ull << q;
+        bm[b] = blocks[b].pauli ? blocks[b].px : dm[b];
+    }
     std::vector<size_t> pending(blocks.size()), rest;
     for (size_t b = 0; b < blocks.size(); ++b) pending[b] = b;
     std::vector<HBlock> ordered;
@@ -174,11 +183,11 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
         for (; i < pending.size(); ++i) {
             if (skipped && scanned_after_skip++ >= kLookahead) break;
             const size_t b = pending[i];
-            if ((bm[b] & blocked) == 0 && __builtin_popcountll(cur | bm[b]) <= t) {
+            if ((dm[b] & blocked) == 0 && __builtin_popcountll(cur | bm[b]) <= t) {
                 cur |= bm[b];
                 ordered.push_back(std::move(blocks[b]));
             } else {
-                blocked |= bm[b];
+                blocked |= dm[b];
                 rest.push_back(b);
                 skipped = true;
             }
@@ -221,8 +230,16 @@ qs_status build_plan(qs_plan_s &p) {
     // Every block (a gate wider than k_max is a block of its own) must fit in a
     // tile next to at least one low qubit, so that qubit 0 is always in the
     // tile and tiles start with a contiguous run.
+    QS_CHECK(o.strategy >= QS_STRATEGY_NONE && o.strategy <= QS_STRATEGY_PAULI, QS_EINVAL, "strategy %d unknown",
+             o.strategy);
     int wmax = o.k_max;
     for (const HGate &g : p.gates) wmax = std::max(wmax, g.nq);
+    std::vector<PauliWindow> win;
+    if (o.strategy == QS_STRATEGY_PAULI) {
+        // X parts up to 8 qubits and below the tile (qubit 0 keeps a slot)
+        win = find_pauli_windows(p.gates, std::min(8, std::min(o.tile_qubits, p.n) - 1));
+        for (const PauliWindow &w : win) wmax = std::max(wmax, __builtin_popcountll(w.x));
+    }
     if (t < p.n)
         QS_CHECK(std::min(wmax, p.n) <= t - 1, QS_EINVAL,
                  "blocks of width %d need a tile of at least %d qubits (got %d)", wmax, wmax + 1, t);
@@ -239,10 +256,50 @@ qs_status build_plan(qs_plan_s &p) {
         }
     } else if (o.strategy == QS_STRATEGY_LEARNED && costmodel_loaded()) {
         return learned_partition(p, t, c);
+    } else if (o.strategy == QS_STRATEGY_PAULI) {
+        // units: each window, and every gate outside the windows, in program
+        // order; a window is a block of its own, the gates merge greedily
+        std::vector<HGate> units;
+        std::vector<char> solo;
+        std::vector<int64_t> first;   // window: its index; gate: its program index
+        size_t wi = 0;
+        for (int64_t gi = 0; gi < (int64_t)p.gates.size();) {
+            if (wi < win.size() && win[wi].begin == gi) {
+                HGate u;
+                u.nq = (int)win[wi].support.size();
+                for (int j = 0; j < u.nq; ++j) u.q[j] = win[wi].support[j];
+                units.push_back(std::move(u));
+                solo.push_back(1);
+                first.push_back((int64_t)wi);
+                gi = win[wi].end;
+                ++wi;
+            } else {
+                units.push_back(p.gates[gi]);
+                solo.push_back(0);
+                first.push_back(gi);
+                ++gi;
+            }
+        }
+        greedy_blocks(units, p.n, o.k_max, p.blocks, &solo);
+        for (HBlock &b : p.blocks) {
+            if (b.members.size() == 1 && solo[b.members[0]]) {
+                const PauliWindow &w = win[first[b.members[0]]];
+                b.pauli = true;
+                b.px = w.x;
+                b.pz = w.z;
+                b.pc = w.c;
+                b.pd = w.d;
+                b.members.clear();
+                for (int64_t gi = w.begin; gi < w.end; ++gi) b.members.push_back(gi);
+            } else {
+                for (int64_t &m : b.members) m = first[m];
+            }
+        }
     } else {
         greedy_blocks(p.gates, p.n, o.k_max, p.blocks);
     }
-    for (HBlock &b : p.blocks) block_matrix(p.gates, b);
+    for (HBlock &b : p.blocks)
+        if (!b.pauli) block_matrix(p.gates, b);
     pack_passes(p, p.blocks, t, c, p.passes);
     return QS_OK;
 }

@@ -313,6 +313,54 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
     }
 }
 
+// ---- Pauli rotation ------------------------------------------------------------
+// y[k] = c psi[k] + d sigma(k ^ x) psi[k ^ x], sigma(j) = (-1)^{|j & z|} over the
+// global index j.  Record: x and z over tile positions, the z bits of qubits
+// outside the tile (their parity is fixed per tile: gbase, the global index of
+// tile position 0, carries them), c, d.  One lane per pair (k, k ^ x), or per
+// amplitude when x = 0 (diagonal).
+template <typename R, int NT = TT>
+__device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
+                                            uint64_t gbase) {
+    using A = typename AmpOf<R>::A;
+    const uint32_t x = pool_bits(E[0]), zt = pool_bits(E[1]);
+    const uint64_t zo = (uint64_t)pool_bits(E[2]) | ((uint64_t)pool_bits(E[3]) << 32);
+    const uint32_t so = (uint32_t)__builtin_popcountll(gbase & zo) & 1u;
+    const R cr = E[4], ci = E[5], dr = E[6], di = E[7];
+    auto sgn = [&](uint32_t j) { return ((uint32_t)__builtin_popcount(j & zt) ^ so) & 1u; };
+    if (x == 0) {
+        const R pr = cr + dr, pi = ci + di, mr = cr - dr, mi = ci - di;
+        for (uint32_t k = threadIdx.x; k < (1u << T); k += NT) {
+            const bool neg = sgn(k);
+            const R fr = neg ? mr : pr, fi = neg ? mi : pi;
+            A &v = tile[sw(k)];
+            const A a = v;
+            A y;
+            y.x = fr * a.x - fi * a.y;
+            y.y = fr * a.y + fi * a.x;
+            v = y;
+        }
+        return;
+    }
+    const int h = 31 - __builtin_clz(x);
+    for (uint32_t g = threadIdx.x; g < (1u << (T - 1)); g += NT) {
+        const uint32_t k0 = ins0_32(g, h), k1 = k0 ^ x;
+        A &v0 = tile[sw(k0)];
+        A &v1 = tile[sw(k1)];
+        const A a = v0, b = v1;
+        // y[k0] takes sigma(k1) psi[k1], y[k1] takes sigma(k0) psi[k0]
+        const R d1r = sgn(k1) ? -dr : dr, d1i = sgn(k1) ? -di : di;
+        const R d0r = sgn(k0) ? -dr : dr, d0i = sgn(k0) ? -di : di;
+        A y0, y1;
+        y0.x = cr * a.x - ci * a.y + d1r * b.x - d1i * b.y;
+        y0.y = cr * a.y + ci * a.x + d1r * b.y + d1i * b.x;
+        y1.x = cr * b.x - ci * b.y + d0r * a.x - d0i * a.y;
+        y1.y = cr * b.y + ci * b.x + d0r * a.y + d0i * a.x;
+        v0 = y0;
+        v1 = y1;
+    }
+}
+
 // ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
 // Y = A X with A = [[Ur, -Ui], [Ui, Ur]] (2D x 2D, D = 2^K) and X the 2D x N
 // real view of the tile (rows: Re then Im of the block's 2^K amplitudes;
@@ -619,11 +667,16 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
 // narrow monomial blocks keep their wave-uniform scalar loads from the pool.
 template <typename R, bool WIDE, bool CL = false, int NT = TT>
 __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                            const R *__restrict__ pool, const R *cst = nullptr, int cl_off = 0) {
+                                            const R *__restrict__ pool, uint64_t gbase, const R *cst = nullptr,
+                                            int cl_off = 0) {
     const int k = bd->k;
     const int kind = bd->kind;
     const R *U = pool + bd->mat_off;
     constexpr bool F32 = sizeof(R) == 4;
+    if (kind == BK_PAULI) {
+        pauli_block<R, NT>(tile, T, U, gbase);
+        return;
+    }
     if (kind == BK_MFMA) {
         if constexpr (CL) {
             const R *As = cst + (bd->mat_off - cl_off);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqsim.so")
 
 QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_ERANGE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 QS_C64, QS_C128 = 0, 1
-STRATEGY_NONE, STRATEGY_GREEDY, STRATEGY_LEARNED = 0, 1, 2
+STRATEGY_NONE, STRATEGY_GREEDY, STRATEGY_LEARNED, STRATEGY_PAULI = 0, 1, 2, 3
 PROF_PLAIN, PROF_TILE, PROF_REDUCE, PROF_EXPECT, PROF_COPY = range(5)
 
 # qsynth gate names -> qs_kind

@@ -302,3 +302,78 @@ def test_learned_strategy_without_model_falls_back_to_greedy(Q):
     finally:
         Q.qs_plan_destroy(a)
         Q.qs_plan_destroy(b)
+
+
+def _pauli_matrix(qs, x, z, theta):
+    """exp(-i theta P) on the qubits qs (local bit j <-> qs[j]) for the Pauli
+    string with X part x and Z part z: cos(theta) I - i sin(theta) P with
+    P|j> = i^|x&z| (-1)^|j&z| |j ^ x>."""
+    D = 1 << len(qs)
+    lx = sum(1 << j for j, q in enumerate(qs) if (x >> q) & 1)
+    lz = sum(1 << j for j, q in enumerate(qs) if (z >> q) & 1)
+    P = np.zeros((D, D), dtype=np.complex128)
+    for j in range(D):
+        P[j ^ lx, j] = (1j) ** bin(lx & lz).count("1") * (-1) ** bin(j & lz).count("1")
+    return np.cos(theta) * np.eye(D) - 1j * np.sin(theta) * P
+
+
+@pytest.mark.parametrize("n,t", [(12, 10), (16, 13), (20, 9)])
+def test_pauli_strategy_recovers_the_rotations(Q, oracle, n, t):
+    """The Pauli strategy contracts each exponential of a UCC circuit (basis
+    changes, CNOT ladder, RZ, ladder and basis changes undone) into one block
+    whose matrix is the rotation the generator drew, exp(-i theta P); the
+    blocks in plan order reproduce the circuit (plan checker)."""
+    c, rots = qsynth.ucc(n, n_exp=30, seed=n)
+    plan, _ = _plan(Q, c, k_max=4, tile_qubits=t, low_qubits=1, strategy=Q.STRATEGY_PAULI)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        assert info.n_blocks == len(rots)
+        qls, mats, mems = [], [], []
+        for b in range(info.n_blocks):
+            qs, U, mem = Q.qs_plan_block(plan, b)
+            qls.append(qs)
+            mats.append(U)
+            mems.append(mem)
+        greedy.check_order(c.gates, mems)
+        for e, b in enumerate(sorted(range(len(mems)), key=lambda b: mems[b][0])):
+            x, z, theta = rots[e]
+            assert np.max(np.abs(mats[b] - _pauli_matrix(qls[b], x, z, theta))) < 1e-13
+        psi0 = qsynth.random_state(n, seed=3)
+        ref = oracle.run(c, psi0.copy())
+        got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
+        assert np.max(np.abs(got - ref)) < 1e-12
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+def test_pauli_strategy_on_mixed_circuits(Q, oracle):
+    """Rotation windows inside other gates: a random circuit, a UCC segment and
+    a brickwork segment back to back.  Windows are found only where a run
+    multiplies to a rotation; everything else is contracted greedily, and the
+    plan reproduces the circuit."""
+    n = 10
+    parts = [qsynth.random_circuit(n, 60, seed=1), qsynth.ucc(n, n_exp=8, seed=2)[0], qsynth.brickwork(n, 3, seed=3),
+             qsynth.ucc(n, n_exp=5, seed=4)[0]]
+    c = qsynth.Circuit(n, [g for p in parts for g in p.gates])
+    plan, _ = _plan(Q, c, k_max=3, tile_qubits=9, strategy=Q.STRATEGY_PAULI)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        qls, mats, mems = [], [], []
+        for b in range(info.n_blocks):
+            qs, U, mem = Q.qs_plan_block(plan, b)
+            qls.append(qs)
+            mats.append(U)
+            mems.append(mem)
+        assert sum(1 for q in qls if len(q) > 3) >= 1   # at least one contracted rotation wider than k_max
+        greedy.check_order(c.gates, mems)
+        psi0 = qsynth.random_state(n, seed=4)
+        ref = oracle.run(c, psi0.copy())
+        got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
+        assert np.max(np.abs(got - ref)) < 1e-12
+    finally:
+        Q.qs_plan_destroy(plan)
+
+
+def test_unknown_strategy_rejected(Q):
+    with pytest.raises(Q.QsimError):
+        _plan(Q, qsynth.ghz(6), strategy=7)

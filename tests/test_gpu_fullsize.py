@@ -154,3 +154,19 @@ def test_large_tiles_30q(Q, t):
     ref = np.exp(1j * ang) / math.sqrt(1 << N)
     assert np.max(np.abs(got - ref)) <= 1e-5 / math.sqrt(1 << N) * 30
     s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("t", [13, 14])
+def test_pauli_strategy_30q_every_nonzero_amplitude(Q, t):
+    """Pauli-rotation contraction at full size: the first 12 exponentials of
+    the benchmark circuit (at most 2^12 nonzero amplitudes), every nonzero
+    amplitude against the closed form."""
+    c, rots = qsynth.ucc(N, n_exp=12, seed=3)
+    s = run(Q, c, 0, k_max=4, tile_qubits=t, low_qubits=4, strategy=Q.STRATEGY_PAULI)
+    exact = sparse_rotations(rots)
+    idx = sorted(exact)
+    got = amps_at(Q, s, idx)
+    assert np.max(np.abs(got - np.array([exact[k] for k in idx]))) <= 1e-5
+    assert abs(s.norm() - 1.0) <= 1e-4
+    s.close()

@@ -242,6 +242,32 @@ def test_fused_block_diagonal_small_states(Q, oracle, dtype, n):
         assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("t", [9, 12, 13, 14])
+def test_pauli_strategy(Q, oracle, dtype, t):
+    """Contracted Pauli rotations on the device: UCC exponentials mixed with
+    Z-only strings (diagonal rotations, no tile qubit needed), rotations whose
+    Z part lies outside the tile (per-tile sign) and a random segment that
+    stays greedy, over several tile sizes."""
+    if dtype == 1 and t > 13:
+        pytest.skip("complex128 tiles stop at 2^13")
+    n = 16
+    rng = np.random.default_rng(t)
+    c, _ = qsynth.ucc(n, n_exp=40, seed=30 + t)
+    for _ in range(6):
+        sup = sorted(int(q) for q in rng.choice(n, size=5, replace=False))
+        qsynth.pauli_exponential(c, [(q, "Z") for q in sup], float(rng.normal(0, 0.5)))
+    for g in qsynth.random_circuit(n, 40, seed=t).gates:
+        c.gates.append(g)
+    for _ in range(6):
+        sup = sorted(int(q) for q in rng.choice(n, size=6, replace=False))
+        qsynth.pauli_exponential(c, [(q, "XYZ"[int(rng.integers(0, 3))]) for q in sup], float(rng.normal(0, 0.5)))
+    psi0 = qsynth.random_state(n, seed=13)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=4, tile_qubits=t, strategy=Q.STRATEGY_PAULI)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
 @pytest.mark.parametrize("renorm", [0, 1])
 def test_renorm_chain(Q, oracle, renorm):
     n = 16
