@@ -327,13 +327,20 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
     const uint64_t zo = (uint64_t)pool_bits(E[2]) | ((uint64_t)pool_bits(E[3]) << 32);
     const uint32_t so = (uint32_t)__builtin_popcountll(gbase & zo) & 1u;
     const R cr = E[4], ci = E[5], dr = E[6], di = E[7];
-    auto sgn = [&](uint32_t j) { return ((uint32_t)__builtin_popcount(j & zt) ^ so) & 1u; };
+    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
+    auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
+    // sign of sigma(j) as a float sign bit: ((|j & zt| + so) & 1) << 31
+    auto sbit = [&](uint32_t j) { return (((uint32_t)__builtin_popcount(j & zt) ^ so) & 1u) << 31; };
+    auto flip = [](R v, uint32_t s) {
+        if constexpr (sizeof(R) == 4) return __uint_as_float(__float_as_uint(v) ^ s);
+        else return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)s << 32));
+    };
     if (x == 0) {
         const R pr = cr + dr, pi = ci + di, mr = cr - dr, mi = ci - di;
         for (uint32_t k = threadIdx.x; k < (1u << T); k += NT) {
-            const bool neg = sgn(k);
+            const bool neg = sbit(k) != 0;
             const R fr = neg ? mr : pr, fi = neg ? mi : pi;
-            A &v = tile[sw(k)];
+            A &v = at(sw(k) * (uint32_t)sizeof(A));
             const A a = v;
             A y;
             y.x = fr * a.x - fi * a.y;
@@ -342,23 +349,38 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
         }
         return;
     }
+    // pairs (k0, k0 ^ x), k0 with bit h of x clear; the swizzle is linear, so
+    // the partner's LDS offset is the pair's XOR a wave-uniform constant, and
+    // sigma(k0 ^ x) = sigma(k0) (-1)^{|x & zt|}
     const int h = 31 - __builtin_clz(x);
-    for (uint32_t g = threadIdx.x; g < (1u << (T - 1)); g += NT) {
-        const uint32_t k0 = ins0_32(g, h), k1 = k0 ^ x;
-        A &v0 = tile[sw(k0)];
-        A &v1 = tile[sw(k1)];
-        const A a = v0, b = v1;
-        // y[k0] takes sigma(k1) psi[k1], y[k1] takes sigma(k0) psi[k0]
-        const R d1r = sgn(k1) ? -dr : dr, d1i = sgn(k1) ? -di : di;
-        const R d0r = sgn(k0) ? -dr : dr, d0i = sgn(k0) ? -di : di;
+    const uint32_t swx = sw(x) * (uint32_t)sizeof(A);
+    const uint32_t sx = ((uint32_t)__builtin_popcount(x & zt) & 1u) << 31;
+    const uint32_t half = 1u << (T - 1);
+    auto pair = [&](uint32_t g) {
+        const uint32_t k0 = ins0_32(g, h);
+        const uint32_t o0 = sw(k0) * (uint32_t)sizeof(A), o1 = o0 ^ swx;
+        const A a = at(o0), b = at(o1);
+        const uint32_t s0 = sbit(k0), s1 = s0 ^ sx;
+        // y[k0] = c a + sigma(k1) d b,  y[k1] = c b + sigma(k0) d a
+        const R d1r = flip(dr, s1), d1i = flip(di, s1), d0r = flip(dr, s0), d0i = flip(di, s0);
         A y0, y1;
         y0.x = cr * a.x - ci * a.y + d1r * b.x - d1i * b.y;
         y0.y = cr * a.y + ci * a.x + d1r * b.y + d1i * b.x;
         y1.x = cr * b.x - ci * b.y + d0r * a.x - d0i * a.y;
         y1.y = cr * b.y + ci * b.x + d0r * a.y + d0i * a.x;
-        v0 = y0;
-        v1 = y1;
+        at(o0) = y0;
+        at(o1) = y1;
+    };
+    if (half >= 2 * NT) {
+        // every lane has exactly half / (2 NT) pairs of pairs: two independent
+        // chains per iteration
+        for (uint32_t g = threadIdx.x; g < half; g += 2 * NT) {
+            pair(g);
+            pair(g + NT);
+        }
+        return;
     }
+    for (uint32_t g = threadIdx.x; g < half; g += NT) pair(g);
 }
 
 // ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
