@@ -351,7 +351,10 @@ def families_mode(a):
     """The paper's circuit families at 20, 25 and 30 qubits, complex64: HEA
     (5 layers RX/RY/RZ + staggered CNOT), QAOA MaxCut (3-regular graph, p = 3)
     and QFT.  Gate-count compression of the contraction at k_max = 2 and at
-    the autotuned width, gate-by-gate vs fused time."""
+    the autotuned width; time gate by gate (one sweep per gate), with every
+    gate a block of its own streamed in the same tile passes (several gates
+    per sweep, no contraction: the role of the paper's multi-gate ablation)
+    and fused."""
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
@@ -366,17 +369,24 @@ def families_mode(a):
             plan = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
                                                low_qubits=best.low_qubits))
             info = Q.qs_plan_info_get(plan)
+            multi = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
+                                                low_qubits=best.low_qubits, strategy=Q.STRATEGY_NONE))
+            minfo = Q.qs_plan_info_get(multi)
             st = Q.State(n, Q.QS_C64)
             ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
+            ms_multi = _timed(lambda: (st.set_basis(0), st.apply_plan(multi)))
             ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
             st.close()
             Q.qs_plan_destroy(plan)
+            Q.qs_plan_destroy(multi)
             S = 8 << n
             rows.append({"family": name, "n": n, "gates": len(c),
                          "compression_k2": round(1 - b2 / len(c), 4),
                          "k_max": best.k_max, "blocks": int(info.n_blocks),
                          "compression": round(1 - info.n_blocks / len(c), 4), "passes": int(info.n_passes),
-                         "plain_ms": round(ms_plain, 2), "fused_ms": round(ms_fused, 2),
+                         "plain_ms": round(ms_plain, 2), "multi_gate_ms": round(ms_multi, 2),
+                         "multi_gate_passes": int(minfo.n_passes),
+                         "multi_gate_speedup": round(ms_plain / ms_multi, 2), "fused_ms": round(ms_fused, 2),
                          "speedup": round(ms_plain / ms_fused, 2),
                          "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1)})
             print(f"[families] {rows[-1]}", file=sys.stderr, flush=True)
