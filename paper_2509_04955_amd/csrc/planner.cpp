@@ -144,7 +144,8 @@ void block_matrix(const std::vector<HGate> &gates, HBlock &b) {
 }
 
 // Passes: list scheduling of the blocks over their dependence order (Section
-// 3.4: blocks sharing a qubit keep their order).  A pass starts from the first
+// 3.4: blocks sharing a qubit keep their order; two Pauli-rotation blocks with
+// commuting strings may swap).  A pass starts from the first
 // pending block and its tile {0..c-1}; pending blocks are scanned in order and
 // a block joins the pass if its qubits fit the tile (at most t qubits).  A block
 // that does not fit is left for a later pass and its qubits are marked: no
@@ -169,6 +170,14 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
         for (int q : blocks[b].qubits) dm[b] |= 1ull << q;
         bm[b] = blocks[b].pauli ? blocks[b].px : dm[b];
     }
+    // Two Pauli-rotation blocks whose strings commute commute as operators
+    // (each is c I + d P), so one may overtake the other although they share
+    // qubits; every other pair sharing a qubit keeps its order.
+    auto commute = [&](size_t a, size_t b) {
+        const HBlock &A = blocks[a], &B = blocks[b];
+        return A.pauli && B.pauli &&
+               ((__builtin_popcountll(A.px & B.pz) + __builtin_popcountll(A.pz & B.px)) & 1) == 0;
+    };
     std::vector<size_t> pending(blocks.size()), rest;
     for (size_t b = 0; b < blocks.size(); ++b) pending[b] = b;
     std::vector<HBlock> ordered;
@@ -183,7 +192,17 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
         for (; i < pending.size(); ++i) {
             if (skipped && scanned_after_skip++ >= kLookahead) break;
             const size_t b = pending[i];
-            if ((dm[b] & blocked) == 0 && __builtin_popcountll(cur | bm[b]) <= t) {
+            bool free = (dm[b] & blocked) == 0;
+            if (!free && blocks[b].pauli) {
+                // overtaking is allowed past skipped blocks it commutes with
+                free = true;
+                for (size_t r : rest)
+                    if ((dm[r] & dm[b]) && !commute(r, b)) {
+                        free = false;
+                        break;
+                    }
+            }
+            if (free && __builtin_popcountll(cur | bm[b]) <= t) {
                 cur |= bm[b];
                 ordered.push_back(std::move(blocks[b]));
             } else {

@@ -321,8 +321,9 @@ def _pauli_matrix(qs, x, z, theta):
 def test_pauli_strategy_recovers_the_rotations(Q, oracle, n, t):
     """The Pauli strategy contracts each exponential of a UCC circuit (basis
     changes, CNOT ladder, RZ, ladder and basis changes undone) into one block
-    whose matrix is the rotation the generator drew, exp(-i theta P); the
-    blocks in plan order reproduce the circuit (plan checker)."""
+    whose matrix is the rotation the generator drew, exp(-i theta P); blocks
+    sharing a qubit run out of program order only when their strings commute,
+    and the blocks in plan order reproduce the circuit (plan checker)."""
     c, rots = qsynth.ucc(n, n_exp=30, seed=n)
     plan, _ = _plan(Q, c, k_max=4, tile_qubits=t, low_qubits=1, strategy=Q.STRATEGY_PAULI)
     try:
@@ -334,10 +335,18 @@ def test_pauli_strategy_recovers_the_rotations(Q, oracle, n, t):
             qls.append(qs)
             mats.append(U)
             mems.append(mem)
-        greedy.check_order(c.gates, mems)
+        rot_of = {}
         for e, b in enumerate(sorted(range(len(mems)), key=lambda b: mems[b][0])):
             x, z, theta = rots[e]
             assert np.max(np.abs(mats[b] - _pauli_matrix(qls[b], x, z, theta))) < 1e-13
+            rot_of[b] = (x, z)
+        swapped = 0
+        for a in range(len(mems)):
+            for b in range(a + 1, len(mems)):
+                if set(qls[a]) & set(qls[b]) and mems[a][0] > mems[b][0]:
+                    (xa, za), (xb, zb) = rot_of[a], rot_of[b]
+                    assert (bin(xa & zb).count("1") + bin(za & xb).count("1")) % 2 == 0
+                    swapped += 1
         psi0 = qsynth.random_state(n, seed=3)
         ref = oracle.run(c, psi0.copy())
         got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
