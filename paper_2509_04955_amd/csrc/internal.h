@@ -50,6 +50,8 @@ enum : int32_t {
     BK_MONO = 2,    // monomial (one nonzero per column): y[dest(c)] = u_c x[c]
     BK_BDIAG = 3,   // permuted block-diagonal: classes of 2^sub rows/columns
     BK_PAULI = 4,   // Pauli rotation: y[k] = c psi[k] + d sigma(k^x) psi[k^x]
+    BK_PAULIG = 5,  // k consecutive Pauli rotations with independent X parts, one lane per coset
+    BK_SKIP = 6,    // folded into the preceding group (no work, no barrier)
 };
 
 struct BlockDev {

@@ -187,6 +187,7 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
         }
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
+            if (blocks[pa.block0 + b].kind == BK_SKIP) continue;   // folded into a group (uniform)
             apply_block<R, WIDE, CL, NT>(tile, T, blocks + pa.block0 + b, pool, base, cst, pa.cl_off);
             __syncthreads();
         }
@@ -315,10 +316,7 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
             threads = 512;
             return k_tile_pass<R, false, 8, true, 512>;
         }
-        if (cl && big_tiles_enabled() && t == 14) {
-            threads = 1024;
-            return k_tile_pass<R, false, 8, true, 1024>;
-        }
+
     }
     if ((1 << t) == vpt * TT * APV) {
         if (cl) {
@@ -348,18 +346,19 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
 size_t lds_operand_budget(int t, qs_dtype dt) {
     constexpr size_t kLds = 160 * 1024, kMargin = 512;
     int wgs = 0;
-    // complex64 2^13 / 2^14 tiles: 2 / 1 workgroups per CU (512 / 1024 threads,
-    // or 2 of 256 threads for 2^13 with QS_TILE_BIG=0)
-    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : t == 14 && big_tiles_enabled() ? 1 : 0;
+    // complex64 2^13 tiles: 2 workgroups per CU (512 threads, or 256 with
+    // QS_TILE_BIG=0); 2^14 tiles are not staged (a staged 1024-thread variant
+    // spills registers at 4 waves per SIMD, and a reload waits for the prefetch)
+    if (dt == QS_C64) wgs = t == 11 ? 4 : t == 12 ? 3 : t == 13 ? 2 : 0;
     else wgs = t == 11 || t == 12 ? 2 : 0;   // complex128 variants run 2 workgroups per CU
     if (!wgs) return 0;
     const size_t share = (kLds / wgs) & ~(size_t)1023, tile = (size_t)(dt == QS_C64 ? 8 : 16) << t;
     return share > tile + kMargin ? share - tile - kMargin : 0;
 }
 
-// Staged complex64 passes in 512 / 1024-thread workgroups apply 5-qubit
-// blocks with the real embedding (the three-product form would spill there).
-bool big_staged(int t, qs_dtype dt) { return dt == QS_C64 && (t == 13 || t == 14) && big_tiles_enabled(); }
+// Staged complex64 passes in 512-thread workgroups apply 5-qubit blocks with
+// the real embedding (the three-product form would spill there).
+bool big_staged(int t, qs_dtype dt) { return dt == QS_C64 && t == 13 && big_tiles_enabled(); }
 
 // Raise a kernel's dynamic LDS limit once per (kernel, size).
 void set_lds_limit(const void *fn, size_t bytes) {
@@ -561,6 +560,94 @@ R pool_entry(uint32_t bits) {
     return v;
 }
 
+bool pauli_groups_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_PAULI_GROUP");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v == 1;
+}
+
+// Rotations from block b on (within the pass ending at `end`) that form one
+// group: at most cap (3), all with X parts that are nonzero and linearly
+// independent over GF(2).
+int pauli_group_size(const std::vector<HBlock> &blocks, int64_t b, int64_t end, int cap) {
+    if (!pauli_groups_enabled()) return 1;
+    std::vector<uint64_t> red;   // echelon basis, each with a distinct leading bit
+    int m = 0;
+    for (int64_t i = b; i < end && m < cap; ++i) {
+        const HBlock &B = blocks[i];
+        if (!B.pauli || B.px == 0) break;
+        uint64_t r = B.px;
+        for (uint64_t v : red)
+            if ((r >> (63 - __builtin_clzll(v))) & 1) r ^= v;
+        if (r == 0) break;
+        red.push_back(r);
+        std::sort(red.begin(), red.end(), [](uint64_t a, uint64_t c) { return a > c; });
+        ++m;
+    }
+    return m;
+}
+
+template <typename R>
+void push_pauli_group(const HBlock *bl, int m, BlockDev &d, const HPass &ps, std::vector<R> &pool) {
+    auto to_tile = [&](uint64_t g, uint64_t *outside) {
+        uint32_t t = 0;
+        uint64_t tmask = 0;
+        for (size_t j = 0; j < ps.tile.size(); ++j) {
+            tmask |= 1ull << ps.tile[j];
+            if ((g >> ps.tile[j]) & 1) t |= 1u << j;
+        }
+        if (outside) *outside = g & ~tmask;
+        return t;
+    };
+    uint32_t xt[4], zt[4];
+    uint64_t zo[4];
+    for (int i = 0; i < m; ++i) {
+        uint64_t xo = 0;
+        xt[i] = to_tile(bl[i].px, &xo);
+        if (xo) throw std::logic_error("Pauli block's X part outside its tile");
+        zt[i] = to_tile(bl[i].pz, &zo[i]);
+    }
+    // pivots: leading bits of an echelon form (each reduced vector is zero at
+    // the earlier pivots), so only 0 in the span is zero at every pivot
+    std::vector<uint32_t> red;
+    std::vector<int> piv;
+    for (int i = 0; i < m; ++i) {
+        uint32_t r = xt[i];
+        for (size_t l = 0; l < red.size(); ++l)
+            if ((r >> piv[l]) & 1) r ^= red[l];
+        if (r == 0) throw std::logic_error("Pauli group X parts not independent");
+        red.push_back(r);
+        piv.push_back(31 - __builtin_clz(r));
+    }
+    std::sort(piv.begin(), piv.end());
+    d.kind = BK_PAULIG;
+    d.k = m;
+    d.mat_off = (int32_t)pool.size();
+    for (int j = 0; j < 4; ++j) pool.push_back(pool_entry<R>(j < m ? (uint32_t)piv[j] : 0u));
+    for (int c = 0; c < 16; ++c) {
+        uint32_t v = 0;
+        for (int j = 0; j < m; ++j)
+            if ((c >> j) & 1) v ^= xt[j];
+        pool.push_back(pool_entry<R>(c < (1 << m) ? sw(v) * 2 * (uint32_t)sizeof(R) : 0u));
+    }
+    for (int i = 0; i < m; ++i) {
+        uint32_t pm = 0;
+        for (int j = 0; j < m; ++j)
+            if (__builtin_popcount(xt[j] & zt[i]) & 1) pm |= 1u << j;
+        pool.push_back(pool_entry<R>(zt[i]));
+        pool.push_back(pool_entry<R>((uint32_t)zo[i]));
+        pool.push_back(pool_entry<R>((uint32_t)(zo[i] >> 32)));
+        pool.push_back(pool_entry<R>(pm));
+        pool.push_back((R)bl[i].pc.real());
+        pool.push_back((R)bl[i].pc.imag());
+        pool.push_back((R)bl[i].pd.real());
+        pool.push_back((R)bl[i].pd.imag());
+    }
+}
+
 template <typename R>
 void push_pauli(const HBlock &blk, BlockDev &d, const HPass &ps, std::vector<R> &pool) {
     uint32_t xt = 0, zt = 0;
@@ -658,6 +745,8 @@ size_t bdiag_width(const HBlock &b) {
 // Real flops per amplitude of one block as the tile kernel applies it.
 double block_flops_per_amp(const BlockDev &d) {
     if (d.kind == BK_PAULI) return 16.0;
+    if (d.kind == BK_PAULIG) return 16.0 * d.k;
+    if (d.kind == BK_SKIP) return 0.0;
     if (d.kind == BK_MONO) return 6.0;
     if (d.kind == BK_BDIAG) return 8.0 * (1 << d.sub);
     return 8.0 * (1 << d.k);
@@ -670,7 +759,7 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
         const HBlock &blk = blocks[i];
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
-        size_t e = kind == BK_PAULI   ? 8
+        size_t e = kind == BK_PAULI   ? 52   // bound: a group record (pivots, 16 offsets, 4 x 8)
                    : kind == BK_MONO    ? 4 * (size_t)D
                    : kind == BK_MFMA  ? (k == 4 || (k == 5 && !big_staged(ps.t, dt)) ? (size_t)3 * D * D
                                                                                       : (size_t)4 * D * D)
@@ -767,8 +856,21 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
             BlockDev &d = hb[b];
             std::memset(&d, 0, sizeof d);
             if (blk.pauli) {
-                if (dt == QS_C64) push_pauli<float>(blk, d, ps, pool32);
-                else push_pauli<double>(blk, d, ps, pool64);
+                // consecutive rotations with independent X parts: one group record
+                int m = pauli_group_size(p.blocks, b, ps.block0 + ps.nblocks, 3);
+                if (m >= 2) {
+                    if (dt == QS_C64) push_pauli_group<float>(&p.blocks[b], m, d, ps, pool32);
+                    else push_pauli_group<double>(&p.blocks[b], m, d, ps, pool64);
+                    for (int j = 1; j < m; ++j) {
+                        std::memset(&hb[b + j], 0, sizeof(BlockDev));
+                        hb[b + j].kind = BK_SKIP;
+                    }
+                    b += m - 1;
+                } else if (dt == QS_C64) {
+                    push_pauli<float>(blk, d, ps, pool32);
+                } else {
+                    push_pauli<double>(blk, d, ps, pool64);
+                }
                 continue;
             }
             d.k = (int)blk.qubits.size();

@@ -383,6 +383,69 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
     for (uint32_t g = threadIdx.x; g < half; g += NT) pair(g);
 }
 
+// ---- group of M Pauli rotations (M = 2, 3) -------------------------------------
+// Consecutive rotations whose X parts x_0..x_{M-1} are linearly independent act
+// on the cosets k0 + span(x_j): one lane loads the 2^M amplitudes of a coset
+// (member c = k0 ^ sum_j c_j x_j), applies the rotations in order in registers
+// (rotation i pairs members c and c ^ 2^i) and stores them.  k0 has zeros at M
+// pivot positions (an echelon form of the x_j), which makes the cosets a
+// partition of the tile.  Record: pivots (4 entries), swizzled byte offsets of
+// the 2^M members (16 entries), then per rotation: z over tile positions, z of
+// the qubits outside the tile (two entries), the parities |x_j & z| as a mask
+// over j, c, d.
+template <typename R, int M, int NT = TT>
+__device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
+                                            uint64_t gbase) {
+    using A = typename AmpOf<R>::A;
+    constexpr int NM = 1 << M;
+    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
+    auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
+    auto flip = [](R v, uint32_t s) {
+        if constexpr (sizeof(R) == 4) return __uint_as_float(__float_as_uint(v) ^ s);
+        else return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)s << 32));
+    };
+    int piv[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) piv[j] = (int)pool_bits(E[j]);
+    const R *Rt = E + 20;
+    const uint32_t G = 1u << (T - M);
+    for (uint32_t g = threadIdx.x; g < G; g += NT) {
+        uint32_t k0 = g;
+#pragma unroll
+        for (int j = 0; j < M; ++j) k0 = ins0_32(k0, piv[j]);
+        const uint32_t base = sw(k0) * (uint32_t)sizeof(A);
+        A v[NM];
+#pragma unroll
+        for (int c = 0; c < NM; ++c) v[c] = at(base ^ pool_bits(E[4 + c]));
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const R *Ri = Rt + 8 * i;
+            const uint32_t zt = pool_bits(Ri[0]);
+            const uint64_t zo = (uint64_t)pool_bits(Ri[1]) | ((uint64_t)pool_bits(Ri[2]) << 32);
+            const uint32_t pm = pool_bits(Ri[3]);
+            const R cr = Ri[4], ci = Ri[5], dr = Ri[6], di = Ri[7];
+            // sign of sigma_i at member c: |k0 & z| + |tile base & z outside| + |c & pm|
+            const uint32_t s0 =
+                (((uint32_t)__builtin_popcount(k0 & zt) ^ (uint32_t)__builtin_popcountll(gbase & zo)) & 1u) << 31;
+#pragma unroll
+            for (int c = 0; c < NM; ++c) {
+                if (c & (1 << i)) continue;
+                const int c2 = c | (1 << i);
+                const uint32_t sc = s0 ^ (((uint32_t)__builtin_popcount((uint32_t)c & pm) & 1u) << 31);
+                const uint32_t sc2 = s0 ^ (((uint32_t)__builtin_popcount((uint32_t)c2 & pm) & 1u) << 31);
+                const A a = v[c], b = v[c2];
+                const R e2r = flip(dr, sc2), e2i = flip(di, sc2), e1r = flip(dr, sc), e1i = flip(di, sc);
+                v[c].x = cr * a.x - ci * a.y + e2r * b.x - e2i * b.y;
+                v[c].y = cr * a.y + ci * a.x + e2r * b.y + e2i * b.x;
+                v[c2].x = cr * b.x - ci * b.y + e1r * a.x - e1i * a.y;
+                v[c2].y = cr * b.y + ci * b.x + e1r * a.y + e1i * a.x;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NM; ++c) at(base ^ pool_bits(E[4 + c])) = v[c];
+    }
+}
+
 // ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
 // Y = A X with A = [[Ur, -Ui], [Ui, Ur]] (2D x 2D, D = 2^K) and X the 2D x N
 // real view of the tile (rows: Re then Im of the block's 2^K amplitudes;
@@ -697,6 +760,11 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     constexpr bool F32 = sizeof(R) == 4;
     if (kind == BK_PAULI) {
         pauli_block<R, NT>(tile, T, U, gbase);
+        return;
+    }
+    if (kind == BK_PAULIG) {
+        if (k == 2) pauli_group<R, 2, NT>(tile, T, U, gbase);
+        else pauli_group<R, 3, NT>(tile, T, U, gbase);
         return;
     }
     if (kind == BK_MFMA) {

@@ -151,9 +151,9 @@ def test_fused_low_qubit_counts(Q, oracle, dtype, low, t):
 def test_fused_mfma_operands_staged_or_not(Q, oracle, n5, n3, t):
     """Passes whose MFMA operands fit the LDS left beside the tile (a dense
     5-qubit block is 12 KB in the three-product form, 16 KB embedded as in
-    the 512/1024-thread workgroups of 2^13/2^14 tiles; 3-qubit blocks 1 KB)
-    stage them there and also run 3-qubit blocks on MFMA; passes over the
-    budget read them from the pool.  Both give the oracle's state."""
+    the 512-thread workgroups of 2^13 tiles; 3-qubit blocks 1 KB) stage them
+    there and also run 3-qubit blocks on MFMA; passes over the budget (and
+    every 2^14 tile) read them from the pool.  Both give the oracle's state."""
     n = 15
     rng = np.random.default_rng(100 * n5 + n3 + t)
 
