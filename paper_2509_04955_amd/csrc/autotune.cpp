@@ -8,7 +8,8 @@
 // the qubits the gates touch (fewer passes) at the price of shorter coalesced
 // runs per tile segment.  Each candidate's plan runs on a scratch state once
 // to warm up and is then timed with hipEvents; circuits longer than
-// kTunePrefix gates are tuned on their first kTunePrefix gates (the passes of
+// kTunePrefix gates are tuned on their first kTunePrefix gates (4 kTunePrefix
+// for the Pauli-rotation strategy; the passes of
 // a long circuit repeat the same structure).  Results are cached per
 // (n, dtype, strategy, gate structure) for the life of the process.
 #include <algorithm>
@@ -55,7 +56,9 @@ extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, si
         b.renorm = 1;
     }
     b.dtype = dtype;
-    const size_t ng = std::min(n_gates, kTunePrefix);
+    // a rotation-contracted plan has a pass per several dozen gates: a longer
+    // prefix gives it as many passes to time as a greedy plan gets
+    const size_t ng = std::min(n_gates, b.strategy == QS_STRATEGY_PAULI ? 4 * kTunePrefix : kTunePrefix);
     const auto key = std::make_tuple(n, (int)dtype, (int)b.strategy, structure_hash(gates, ng));
     {
         std::lock_guard<std::mutex> lk(g_mu);
