@@ -55,6 +55,22 @@ def test_batch_mixed_block_kinds(Q, oracle):
     b.close()
 
 
+@pytest.mark.parametrize("dtype,tol", [(0, 1e-5), (1, 1e-12)])
+def test_batch_pauli_rotation_plans(Q, oracle, dtype, tol):
+    """UCC states of 10..16 qubits under the Pauli-rotation contraction in the
+    batch kernel: rotation blocks, grouped rotations and their per-tile signs
+    (Z parts outside the tile) go through the same block dispatch."""
+    circuits = [qsynth.ucc(n, n_exp=25, seed=40 + n)[0] for n in (10, 12, 13, 16)]
+    hams = [qsynth.random_pauli_sum(c.n, 16, seed=(5, c.n)) for c in circuits]
+    b = Q.Batch(circuits, hams, Q.opts(k_max=4, tile_qubits=10, dtype=dtype, strategy=Q.STRATEGY_PAULI))
+    E = b.run()
+    for i, (c, h) in enumerate(zip(circuits, hams)):
+        psi, e = _oracle_energy(oracle, c, h)
+        assert abs(E[i] - e) <= tol * max(1, abs(e)), (i, c.n, E[i], e)
+        assert oracle.max_abs(psi, b.amplitudes(i)) <= tol
+    b.close()
+
+
 def test_batch_autotuned(Q, oracle):
     """k_max = 0 asks the autotuner for every distinct qubit count."""
     circuits, hams = qsynth.hea_batch(10, 12, 17, layers=8, n_terms=20, seed=9)
