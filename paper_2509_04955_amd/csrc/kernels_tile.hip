@@ -560,6 +560,18 @@ R pool_entry(uint32_t bits) {
     return v;
 }
 
+// Coefficient form of a rotation for the device (rot_pair): 1 when c is real
+// and d imaginary (a Pauli exponential whose Clifford part cancels exactly),
+// 2 when both are real, else 0.  Parts below 1e-15 are rounding residue of
+// exact zeros (the Clifford phase is simulated in FP64).
+int pauli_mode(const HBlock &b) {
+    const double tol = 1e-15;
+    if (std::abs(b.pc.imag()) > tol) return 0;
+    if (std::abs(b.pd.real()) <= tol) return 1;
+    if (std::abs(b.pd.imag()) <= tol) return 2;
+    return 0;
+}
+
 bool pauli_groups_enabled() {
     static int v = -1;
     if (v < 0) {
@@ -626,7 +638,10 @@ void push_pauli_group(const HBlock *bl, int m, BlockDev &d, const HPass &ps, std
     d.kind = BK_PAULIG;
     d.k = m;
     d.mat_off = (int32_t)pool.size();
-    for (int j = 0; j < 4; ++j) pool.push_back(pool_entry<R>(j < m ? (uint32_t)piv[j] : 0u));
+    uint32_t modes = 0;
+    for (int i = 0; i < m; ++i) modes |= (uint32_t)pauli_mode(bl[i]) << (2 * i);
+    for (int j = 0; j < 3; ++j) pool.push_back(pool_entry<R>(j < m ? (uint32_t)piv[j] : 0u));
+    pool.push_back(pool_entry<R>(modes));
     for (int c = 0; c < 16; ++c) {
         uint32_t v = 0;
         for (int j = 0; j < m; ++j)
@@ -662,6 +677,7 @@ void push_pauli(const HBlock &blk, BlockDev &d, const HPass &ps, std::vector<R> 
     const uint64_t zo = blk.pz & ~tmask;
     d.kind = BK_PAULI;
     d.k = __builtin_popcount(xt);
+    d.sub = pauli_mode(blk);
     d.mat_off = (int32_t)pool.size();
     pool.push_back(pool_entry<R>(xt));
     pool.push_back(pool_entry<R>(zt));

@@ -12,6 +12,8 @@
 //     one complex multiply per amplitude and a permuted write.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -313,15 +315,47 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
     }
 }
 
+// One Pauli-rotation pair update: y0 = c a + sigma1 d b, y1 = c b + sigma0 d a,
+// sigma as float sign bits s0, s1.  MODE 0: c, d complex; 1: c real, d = i*dI
+// (Pauli exponentials without a phase: 4 products per output instead of 8);
+// 2: c and d real.
+template <int MODE, typename A, typename R>
+__device__ __forceinline__ void rot_pair(A &y0, A &y1, const A a, const A b, uint32_t s0, uint32_t s1, R cr, R ci,
+                                         R dr, R di) {
+    auto flip = [](R v, uint32_t s) {
+        if constexpr (sizeof(R) == 4) return __uint_as_float(__float_as_uint(v) ^ s);
+        else return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)s << 32));
+    };
+    if constexpr (MODE == 1) {
+        const R e1 = flip(di, s1), e0 = flip(di, s0);
+        y0.x = cr * a.x - e1 * b.y;
+        y0.y = cr * a.y + e1 * b.x;
+        y1.x = cr * b.x - e0 * a.y;
+        y1.y = cr * b.y + e0 * a.x;
+    } else if constexpr (MODE == 2) {
+        const R e1 = flip(dr, s1), e0 = flip(dr, s0);
+        y0.x = cr * a.x + e1 * b.x;
+        y0.y = cr * a.y + e1 * b.y;
+        y1.x = cr * b.x + e0 * a.x;
+        y1.y = cr * b.y + e0 * a.y;
+    } else {
+        const R e1r = flip(dr, s1), e1i = flip(di, s1), e0r = flip(dr, s0), e0i = flip(di, s0);
+        y0.x = cr * a.x - ci * a.y + e1r * b.x - e1i * b.y;
+        y0.y = cr * a.y + ci * a.x + e1r * b.y + e1i * b.x;
+        y1.x = cr * b.x - ci * b.y + e0r * a.x - e0i * a.y;
+        y1.y = cr * b.y + ci * b.x + e0r * a.y + e0i * a.x;
+    }
+}
+
 // ---- Pauli rotation ------------------------------------------------------------
 // y[k] = c psi[k] + d sigma(k ^ x) psi[k ^ x], sigma(j) = (-1)^{|j & z|} over the
 // global index j.  Record: x and z over tile positions, the z bits of qubits
 // outside the tile (their parity is fixed per tile: gbase, the global index of
 // tile position 0, carries them), c, d.  One lane per pair (k, k ^ x), or per
 // amplitude when x = 0 (diagonal).
-template <typename R, int NT = TT>
-__device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
-                                            uint64_t gbase) {
+template <typename R, int NT, int MODE>
+__device__ __forceinline__ void pauli_block_m(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
+                                              uint64_t gbase) {
     using A = typename AmpOf<R>::A;
     const uint32_t x = pool_bits(E[0]), zt = pool_bits(E[1]);
     const uint64_t zo = (uint64_t)pool_bits(E[2]) | ((uint64_t)pool_bits(E[3]) << 32);
@@ -331,10 +365,6 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
     auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
     // sign of sigma(j) as a float sign bit: ((|j & zt| + so) & 1) << 31
     auto sbit = [&](uint32_t j) { return (((uint32_t)__builtin_popcount(j & zt) ^ so) & 1u) << 31; };
-    auto flip = [](R v, uint32_t s) {
-        if constexpr (sizeof(R) == 4) return __uint_as_float(__float_as_uint(v) ^ s);
-        else return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)s << 32));
-    };
     if (x == 0) {
         const R pr = cr + dr, pi = ci + di, mr = cr - dr, mi = ci - di;
         for (uint32_t k = threadIdx.x; k < (1u << T); k += NT) {
@@ -361,13 +391,8 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
         const uint32_t o0 = sw(k0) * (uint32_t)sizeof(A), o1 = o0 ^ swx;
         const A a = at(o0), b = at(o1);
         const uint32_t s0 = sbit(k0), s1 = s0 ^ sx;
-        // y[k0] = c a + sigma(k1) d b,  y[k1] = c b + sigma(k0) d a
-        const R d1r = flip(dr, s1), d1i = flip(di, s1), d0r = flip(dr, s0), d0i = flip(di, s0);
         A y0, y1;
-        y0.x = cr * a.x - ci * a.y + d1r * b.x - d1i * b.y;
-        y0.y = cr * a.y + ci * a.x + d1r * b.y + d1i * b.x;
-        y1.x = cr * b.x - ci * b.y + d0r * a.x - d0i * a.y;
-        y1.y = cr * b.y + ci * b.x + d0r * a.y + d0i * a.x;
+        rot_pair<MODE>(y0, y1, a, b, s0, s1, cr, ci, dr, di);
         at(o0) = y0;
         at(o1) = y1;
     };
@@ -383,16 +408,25 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
     for (uint32_t g = threadIdx.x; g < half; g += NT) pair(g);
 }
 
+// mode (BlockDev.sub): coefficient form, see rot_pair
+template <typename R, int NT = TT>
+__device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
+                                            uint64_t gbase, int mode) {
+    if (mode == 1) pauli_block_m<R, NT, 1>(tile, T, E, gbase);
+    else if (mode == 2) pauli_block_m<R, NT, 2>(tile, T, E, gbase);
+    else pauli_block_m<R, NT, 0>(tile, T, E, gbase);
+}
+
 // ---- group of M Pauli rotations (M = 2, 3) -------------------------------------
 // Consecutive rotations whose X parts x_0..x_{M-1} are linearly independent act
 // on the cosets k0 + span(x_j): one lane loads the 2^M amplitudes of a coset
 // (member c = k0 ^ sum_j c_j x_j), applies the rotations in order in registers
 // (rotation i pairs members c and c ^ 2^i) and stores them.  k0 has zeros at M
 // pivot positions (an echelon form of the x_j), which makes the cosets a
-// partition of the tile.  Record: pivots (4 entries), swizzled byte offsets of
-// the 2^M members (16 entries), then per rotation: z over tile positions, z of
-// the qubits outside the tile (two entries), the parities |x_j & z| as a mask
-// over j, c, d.
+// partition of the tile.  Record: pivots (3 entries), the rotations' coefficient
+// forms (2 bits each, see rot_pair), swizzled byte offsets of the 2^M members
+// (16 entries), then per rotation: z over tile positions, z of the qubits
+// outside the tile (two entries), the parities |x_j & z| as a mask over j, c, d.
 template <typename R, int M, int NT = TT>
 __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
                                             uint64_t gbase) {
@@ -400,13 +434,10 @@ __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, c
     constexpr int NM = 1 << M;
     unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
     auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
-    auto flip = [](R v, uint32_t s) {
-        if constexpr (sizeof(R) == 4) return __uint_as_float(__float_as_uint(v) ^ s);
-        else return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)s << 32));
-    };
     int piv[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) piv[j] = (int)pool_bits(E[j]);
+    const uint32_t modes = pool_bits(E[3]);   // 2 bits per rotation (M <= 3 leaves slot 3 free)
     const R *Rt = E + 20;
     const uint32_t G = 1u << (T - M);
     for (uint32_t g = threadIdx.x; g < G; g += NT) {
@@ -424,22 +455,25 @@ __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, c
             const uint64_t zo = (uint64_t)pool_bits(Ri[1]) | ((uint64_t)pool_bits(Ri[2]) << 32);
             const uint32_t pm = pool_bits(Ri[3]);
             const R cr = Ri[4], ci = Ri[5], dr = Ri[6], di = Ri[7];
+            const uint32_t mode = (modes >> (2 * i)) & 3u;
             // sign of sigma_i at member c: |k0 & z| + |tile base & z outside| + |c & pm|
             const uint32_t s0 =
                 (((uint32_t)__builtin_popcount(k0 & zt) ^ (uint32_t)__builtin_popcountll(gbase & zo)) & 1u) << 31;
+            auto rot = [&](auto mode_tag) {
+                constexpr int MD = decltype(mode_tag)::value;
 #pragma unroll
-            for (int c = 0; c < NM; ++c) {
-                if (c & (1 << i)) continue;
-                const int c2 = c | (1 << i);
-                const uint32_t sc = s0 ^ (((uint32_t)__builtin_popcount((uint32_t)c & pm) & 1u) << 31);
-                const uint32_t sc2 = s0 ^ (((uint32_t)__builtin_popcount((uint32_t)c2 & pm) & 1u) << 31);
-                const A a = v[c], b = v[c2];
-                const R e2r = flip(dr, sc2), e2i = flip(di, sc2), e1r = flip(dr, sc), e1i = flip(di, sc);
-                v[c].x = cr * a.x - ci * a.y + e2r * b.x - e2i * b.y;
-                v[c].y = cr * a.y + ci * a.x + e2r * b.y + e2i * b.x;
-                v[c2].x = cr * b.x - ci * b.y + e1r * a.x - e1i * a.y;
-                v[c2].y = cr * b.y + ci * b.x + e1r * a.y + e1i * a.x;
-            }
+                for (int c = 0; c < NM; ++c) {
+                    if (c & (1 << i)) continue;
+                    const int c2 = c | (1 << i);
+                    const uint32_t sc = s0 ^ (((uint32_t)__builtin_popcount((uint32_t)c & pm) & 1u) << 31);
+                    const uint32_t sc2 = s0 ^ (((uint32_t)__builtin_popcount((uint32_t)c2 & pm) & 1u) << 31);
+                    const A a = v[c], b = v[c2];
+                    rot_pair<MD>(v[c], v[c2], a, b, sc, sc2, cr, ci, dr, di);
+                }
+            };
+            if (mode == 1) rot(std::integral_constant<int, 1>());
+            else if (mode == 2) rot(std::integral_constant<int, 2>());
+            else rot(std::integral_constant<int, 0>());
         }
 #pragma unroll
         for (int c = 0; c < NM; ++c) at(base ^ pool_bits(E[4 + c])) = v[c];
@@ -759,7 +793,7 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     const R *U = pool + bd->mat_off;
     constexpr bool F32 = sizeof(R) == 4;
     if (kind == BK_PAULI) {
-        pauli_block<R, NT>(tile, T, U, gbase);
+        pauli_block<R, NT>(tile, T, U, gbase, bd->sub);
         return;
     }
     if (kind == BK_PAULIG) {
