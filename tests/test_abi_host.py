@@ -386,3 +386,45 @@ def test_pauli_strategy_on_mixed_circuits(Q, oracle):
 def test_unknown_strategy_rejected(Q):
     with pytest.raises(Q.QsimError):
         _plan(Q, qsynth.ghz(6), strategy=7)
+
+
+def test_pauli_strategy_without_windows_is_greedy(Q):
+    """Circuits with no run equal to a rotation (random U3 + CNOT, QFT) get the
+    greedy plan's blocks under the Pauli strategy."""
+    for c in (qsynth.random_u3_cnot(12, 6, seed=3), qsynth.qft(10)):
+        a, _ = _plan(Q, c, k_max=4, tile_qubits=9)
+        b, _ = _plan(Q, c, k_max=4, tile_qubits=9, strategy=Q.STRATEGY_PAULI)
+        try:
+            na, nb = Q.qs_plan_info_get(a).n_blocks, Q.qs_plan_info_get(b).n_blocks
+            assert na == nb
+            ma = sorted(tuple(Q.qs_plan_block(a, i, False)[2]) for i in range(na))
+            mb = sorted(tuple(Q.qs_plan_block(b, i, False)[2]) for i in range(nb))
+            assert ma == mb
+        finally:
+            Q.qs_plan_destroy(a)
+            Q.qs_plan_destroy(b)
+
+
+@pytest.mark.parametrize("t", [9, 12, 14])
+def test_pauli_plan_tiles_hold_x_supports(Q, t):
+    """Every pass tile holds qubit 0 and the X part of each rotation block in
+    it (the Z part may lie outside), and pass ranges cover the blocks."""
+    n = 20
+    c, rots = qsynth.ucc(n, n_exp=60, seed=t)
+    plan, _ = _plan(Q, c, k_max=4, tile_qubits=t, low_qubits=2, strategy=Q.STRATEGY_PAULI)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        mems = [Q.qs_plan_block(plan, b, False)[2] for b in range(info.n_blocks)]
+        start = sorted(range(len(mems)), key=lambda b: mems[b][0])
+        xmask = {b: rots[e][0] for e, b in enumerate(start)}
+        nxt = 0
+        for i in range(info.n_passes):
+            tt, tile, fb, nb = Q.qs_plan_pass(plan, i)
+            assert fb == nxt and nb >= 1 and 0 in tile and len(tile) == t
+            nxt += nb
+            tmask = sum(1 << q for q in tile)
+            for b in range(fb, fb + nb):
+                assert xmask[b] & ~tmask == 0
+        assert nxt == info.n_blocks
+    finally:
+        Q.qs_plan_destroy(plan)
