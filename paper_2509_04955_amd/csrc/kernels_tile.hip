@@ -873,7 +873,9 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
             std::memset(&d, 0, sizeof d);
             if (blk.pauli) {
                 // consecutive rotations with independent X parts: one group record
-                int m = pauli_group_size(p.blocks, b, ps.block0 + ps.nblocks, 3);
+                // (single-state kernel only: plans uploaded for the batch
+                // kernel, stage_lds false, keep one record per rotation)
+                int m = stage_lds ? pauli_group_size(p.blocks, b, ps.block0 + ps.nblocks, 3) : 1;
                 if (m >= 2) {
                     if (dt == QS_C64) push_pauli_group<float>(&p.blocks[b], m, d, ps, pool32);
                     else push_pauli_group<double>(&p.blocks[b], m, d, ps, pool64);

@@ -784,7 +784,9 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
 // three-product form; FP32 or FP64 matrix cores) and monomial
 // blocks with k >= 4 (per-lane records) read them there, dense VALU blocks and
 // narrow monomial blocks keep their wave-uniform scalar loads from the pool.
-template <typename R, bool WIDE, bool CL = false, int NT = TT>
+// PG: rotation groups and coefficient forms compiled in (the single-state pass
+// kernel); the batch kernel leaves them out to keep its register budget.
+template <typename R, bool WIDE, bool CL = false, int NT = TT, bool PG = true>
 __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
                                             const R *__restrict__ pool, uint64_t gbase, const R *cst = nullptr,
                                             int cl_off = 0) {
@@ -793,13 +795,16 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     const R *U = pool + bd->mat_off;
     constexpr bool F32 = sizeof(R) == 4;
     if (kind == BK_PAULI) {
-        pauli_block<R, NT>(tile, T, U, gbase, bd->sub);
+        if constexpr (PG) pauli_block<R, NT>(tile, T, U, gbase, bd->sub);
+        else pauli_block_m<R, NT, 0>(tile, T, U, gbase);
         return;
     }
-    if (kind == BK_PAULIG) {
-        if (k == 2) pauli_group<R, 2, NT>(tile, T, U, gbase);
-        else pauli_group<R, 3, NT>(tile, T, U, gbase);
-        return;
+    if constexpr (PG) {
+        if (kind == BK_PAULIG) {
+            if (k == 2) pauli_group<R, 2, NT>(tile, T, U, gbase);
+            else pauli_group<R, 3, NT>(tile, T, U, gbase);
+            return;
+        }
     }
     if (kind == BK_MFMA) {
         if constexpr (CL) {
