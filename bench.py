@@ -353,8 +353,8 @@ def families_mode(a):
     and QFT.  Gate-count compression of the contraction at k_max = 2 and at
     the autotuned width; time gate by gate (one sweep per gate), with every
     gate a block of its own streamed in the same tile passes (several gates
-    per sweep, no contraction: the role of the paper's multi-gate ablation)
-    and fused."""
+    per sweep, no contraction: the role of the paper's multi-gate ablation),
+    fused, and fused with Pauli-rotation contraction (strategy 3)."""
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
@@ -372,13 +372,20 @@ def families_mode(a):
             multi = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
                                                 low_qubits=best.low_qubits, strategy=Q.STRATEGY_NONE))
             minfo = Q.qs_plan_info_get(multi)
+            # Pauli-rotation contraction in the same tile shape (QAOA's ZZ terms
+            # become diagonal rotations that need no tile qubit)
+            rot = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
+                                              low_qubits=best.low_qubits, strategy=Q.STRATEGY_PAULI))
+            rinfo = Q.qs_plan_info_get(rot)
             st = Q.State(n, Q.QS_C64)
             ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
             ms_multi = _timed(lambda: (st.set_basis(0), st.apply_plan(multi)))
             ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
+            ms_rot = _timed(lambda: (st.set_basis(0), st.apply_plan(rot)))
             st.close()
             Q.qs_plan_destroy(plan)
             Q.qs_plan_destroy(multi)
+            Q.qs_plan_destroy(rot)
             S = 8 << n
             rows.append({"family": name, "n": n, "gates": len(c),
                          "compression_k2": round(1 - b2 / len(c), 4),
@@ -388,6 +395,8 @@ def families_mode(a):
                          "multi_gate_passes": int(minfo.n_passes),
                          "multi_gate_speedup": round(ms_plain / ms_multi, 2), "fused_ms": round(ms_fused, 2),
                          "speedup": round(ms_plain / ms_fused, 2),
+                         "rotation_passes": int(rinfo.n_passes), "rotation_ms": round(ms_rot, 2),
+                         "rotation_speedup": round(ms_plain / ms_rot, 2),
                          "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1)})
             print(f"[families] {rows[-1]}", file=sys.stderr, flush=True)
     print(json.dumps({"mode": "families", "rows": rows}), flush=True)

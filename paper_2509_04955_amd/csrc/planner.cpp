@@ -257,6 +257,13 @@ qs_status build_plan(qs_plan_s &p) {
     if (o.strategy == QS_STRATEGY_PAULI) {
         // X parts up to 8 qubits and below the tile (qubit 0 keeps a slot)
         win = find_pauli_windows(p.gates, std::min(8, std::min(o.tile_qubits, p.n) - 1));
+        // a diagonal rotation (no X part) no wider than k_max is left to the
+        // greedy rule, which merges several of them (and their neighbours)
+        // into one diagonal block: one block per rotation would cost a tile
+        // round trip each (QAOA's ZZ terms)
+        win.erase(std::remove_if(win.begin(), win.end(),
+                                 [&](const PauliWindow &w) { return w.x == 0 && (int)w.support.size() <= o.k_max; }),
+                  win.end());
         for (const PauliWindow &w : win) wmax = std::max(wmax, __builtin_popcountll(w.x));
     }
     if (t < p.n)
