@@ -98,6 +98,9 @@ def parse():
                          "plain12: 12-qubit random circuit, complex128, gate-by-gate vs the FP64 oracle; "
                          "families: the paper's circuit families (HEA, QAOA, QFT) at 20/25/30 qubits")
     ap.add_argument("--states", type=int, default=256)
+    ap.add_argument("--circuit", default="random", choices=["random", "ucc"],
+                    help="learned mode: the evaluated circuit (random U3 + CNOT depth 30, or the UCC workload "
+                         "with --n-exp exponentials)")
     ap.add_argument("--train-n", type=int, default=28,
                     help="learned mode: the cost model is trained on passes at this and one fewer qubit")
     return ap.parse_args()
@@ -203,7 +206,7 @@ def learned_mode(a):
         print(f"[learned] {msg}", file=sys.stderr, flush=True)
 
     n = a.n
-    c = qsynth.random_u3_cnot(n, 30, seed=5)
+    c = qsynth.random_u3_cnot(n, 30, seed=5) if a.circuit == "random" else qsynth.ucc(n, a.n_exp, seed=a.seed)[0]
     gl = Q.GateList(c)
     # the greedy reference gets its best fixed configuration, autotuned on the
     # circuit's first 400 gates; the cost model is trained and the learned
@@ -235,7 +238,8 @@ def learned_mode(a):
     # benchmark family (seed 6, not the evaluated seed 5) at train_n + 2 qubits
     t0 = time.perf_counter()
     n_ref = min(n, a.train_n + 2)
-    ref_circuits = [qsynth.random_u3_cnot(n_ref, 30, seed=6)]
+    ref_circuits = ([qsynth.random_u3_cnot(n_ref, 30, seed=6)] if a.circuit == "random"
+                    else [qsynth.ucc(n_ref, 100, seed=6)[0]])
     X, y, loss = CM.refine(X, y, ref_circuits, rounds=2, **kw)
     refine_s = time.perf_counter() - t0
     corr = float(np.corrcoef(CM.predict(X), y)[0, 1])
@@ -289,7 +293,8 @@ def learned_mode(a):
     norm_cc = st.norm()
     Q.qs_plan_destroy(lb)
     progress(f"C C^dagger |0>: |a0|^2 = {abs(a0) ** 2:.9f}, norm {norm_cc:.12f}")
-    out = {"mode": "learned", "n": n, "gates": len(c), "greedy_config": kw, "autotune_s": round(tune_s, 1),
+    out = {"mode": "learned", "circuit": a.circuit, "n": n, "gates": len(c), "greedy_config": kw,
+           "autotune_s": round(tune_s, 1),
            "train_rows": int(len(y)), "train_loss": loss, "refine_s": round(refine_s, 1),
            "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
            "greedy": {"passes": int(ig.n_passes), "blocks": int(ig.n_blocks), "ms": round(ms_g, 2),
