@@ -853,7 +853,26 @@ bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt
     return per_lane && !dense_wide && pass_operand_bytes(blocks, ps, dt) <= budget;
 }
 
+namespace {
+qs_status plan_upload_impl(qs_plan_s &p, qs_dtype dt, bool stage_lds);
+}  // namespace
+
+// Host invariants of the records (a rotation's X part inside its tile, a
+// group's independent X parts) throw; no exception leaves through the ABI.
 qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
+    try {
+        return plan_upload_impl(p, dt, stage_lds);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed while uploading a plan");
+        return QS_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error("plan upload: %s", e.what());
+        return QS_EINVAL;
+    }
+}
+
+namespace {
+qs_status plan_upload_impl(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
     const int di = dt == QS_C64 ? 0 : 1;
     if (p.dev_ready[di]) return QS_OK;
     std::vector<BlockDev> hb(p.blocks.size());
@@ -918,6 +937,7 @@ qs_status plan_upload(qs_plan_s &p, qs_dtype dt, bool stage_lds) {
     p.dev_ready[di] = 1;
     return QS_OK;
 }
+}  // namespace
 
 qs_status ensure_partials(qs_state_s &s, size_t count) {
     if (s.partials_cap >= count) return QS_OK;
