@@ -241,6 +241,7 @@ qs_status qs_norm(qs_state s, double *out) {
 }
 
 qs_status qs_apply_gates(qs_state s, const qs_gate *gates, size_t n_gates) {
+    QS_ABI_TRY
     QS_CHECK(s != nullptr, QS_EINVAL, "null state");
     std::vector<HGate> hg;
     qs_status st = convert_gates(s->n, gates, n_gates, hg);
@@ -252,6 +253,7 @@ qs_status qs_apply_gates(qs_state s, const qs_gate *gates, size_t n_gates) {
         if (st != QS_OK) return st;
     }
     return QS_OK;
+    QS_ABI_CATCH
 }
 
 qs_status qs_contract(int n, const qs_gate *gates, size_t n_gates, const qs_contract_opts *opts, qs_plan *out) {
@@ -266,10 +268,11 @@ qs_status qs_contract(int n, const qs_gate *gates, size_t n_gates, const qs_cont
         p->opts.strategy = QS_STRATEGY_GREEDY;
         p->opts.renorm = 1;
     }
-    qs_status st = convert_gates(n, gates, n_gates, p->gates);
-    if (st == QS_OK) {
+    qs_status st = QS_OK;
+    {
         try {
-            st = build_plan(*p);
+            st = convert_gates(n, gates, n_gates, p->gates);
+            if (st == QS_OK) st = build_plan(*p);
         } catch (const std::bad_alloc &) {
             set_error("host allocation failed while planning");
             st = QS_ENOMEM;
@@ -309,6 +312,7 @@ qs_status qs_plan_info_get(qs_plan p, qs_plan_info *info) {
 
 qs_status qs_plan_block(qs_plan p, uint64_t b, int *k, int *qubits, double *matrix, uint64_t *members,
                         uint64_t member_cap, uint64_t *n_members) {
+    QS_ABI_TRY
     QS_CHECK(p != nullptr, QS_EINVAL, "null plan");
     QS_CHECK(b < p->blocks.size(), QS_EINVAL, "block index out of range");
     const HBlock &B = p->blocks[b];
@@ -334,6 +338,7 @@ qs_status qs_plan_block(qs_plan p, uint64_t b, int *k, int *qubits, double *matr
         for (uint64_t i = 0; i < std::min<uint64_t>(member_cap, B.members.size()); ++i) members[i] = B.members[i];
     if (n_members) *n_members = B.members.size();
     return QS_OK;
+    QS_ABI_CATCH
 }
 
 qs_status qs_plan_pass(qs_plan p, uint64_t i, int *t, int *tile_qubits, uint64_t *first_block, uint64_t *n_blocks) {

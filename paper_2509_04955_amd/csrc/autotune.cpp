@@ -46,6 +46,7 @@ std::map<std::tuple<int, int, int, uint64_t>, qs_contract_opts> g_cache;
 
 extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, size_t n_gates,
                                  const qs_contract_opts *base, qs_contract_opts *best) {
+    QS_ABI_TRY
     QS_CHECK(best != nullptr && (gates != nullptr || n_gates == 0), QS_EINVAL, "null argument");
     // the scratch state is a full state (2^34 complex64 = 128 GiB at the limit)
     QS_CHECK(n >= 1 && n <= 34, QS_EINVAL, "autotune supports 1 <= n <= 34 (got %d)", n);
@@ -137,4 +138,5 @@ extern "C" qs_status qs_autotune(int n, qs_dtype dtype, const qs_gate *gates, si
     }
     *best = win;
     return QS_OK;
+    QS_ABI_CATCH
 }

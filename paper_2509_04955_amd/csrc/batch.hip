@@ -560,6 +560,7 @@ extern "C" {
 qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *const *circuits, const size_t *n_gates,
                           const uint64_t *const *x, const uint64_t *const *z, const double *const *coeff,
                           const size_t *n_terms, const qs_contract_opts *opts, void *stream, qs_batch *out) {
+    QS_ABI_TRY
     QS_CHECK(out && n_qubits && circuits && n_gates && x && z && coeff && n_terms, QS_EINVAL, "null argument");
     QS_CHECK(n_states >= 1 && n_states <= 65536, QS_EINVAL, "n_states %d outside 1..65536", n_states);
     qs_contract_opts base{};
@@ -768,6 +769,7 @@ qs_status qs_batch_create(int n_states, const int *n_qubits, const qs_gate *cons
     if (e != hipSuccess) return fail(hip_fail(e, "hipGraphInstantiate"));
     *out = b;
     return QS_OK;
+    QS_ABI_CATCH
 }
 
 qs_status qs_batch_destroy(qs_batch b) {

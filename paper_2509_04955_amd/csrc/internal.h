@@ -7,6 +7,8 @@
 #include <complex>
 #include <cstdint>
 #include <string>
+#include <new>
+#include <stdexcept>
 #include <vector>
 
 #include "../../include/qsim.h"
@@ -17,6 +19,20 @@ using cd = std::complex<double>;
 
 // ------------------------------------------------------------- errors
 void set_error(const char *fmt, ...);
+
+// Host work behind an ABI call: allocation failures and violated planner
+// invariants become status codes instead of leaving through extern "C".
+#define QS_ABI_TRY try {
+#define QS_ABI_CATCH                                                         \
+    }                                                                        \
+    catch (const std::bad_alloc &) {                                         \
+        qs::set_error("host allocation failed");                             \
+        return QS_ENOMEM;                                                    \
+    }                                                                        \
+    catch (const std::exception &e) {                                        \
+        qs::set_error("%s", e.what());                                       \
+        return QS_EINVAL;                                                    \
+    }
 qs_status hip_fail(hipError_t e, const char *what);
 
 #define QS_HIP(call)                                         \

@@ -328,14 +328,17 @@ qs_status qs_costmodel_train(const float *features, const float *targets, int n_
 }
 
 qs_status qs_plan_pass_features(qs_plan p, float *out, uint64_t cap_rows) {
+    QS_ABI_TRY
     QS_CHECK(p && out, QS_EINVAL, "null argument");
     QS_CHECK(cap_rows >= p->passes.size(), QS_ERANGE, "need %zu rows", p->passes.size());
     const qs_dtype dt = p->opts.dtype == QS_C128 ? QS_C128 : QS_C64;
     for (size_t i = 0; i < p->passes.size(); ++i) pass_features(p->n, dt, p->passes[i], p->blocks, out + i * kNumFeatures);
     return QS_OK;
+    QS_ABI_CATCH
 }
 
 qs_status qs_plan_time_passes(qs_plan p, qs_dtype dtype, int reps, double *us_out) {
+    QS_ABI_TRY
     QS_CHECK(p && us_out, QS_EINVAL, "null argument");
     QS_CHECK(reps >= 1 && reps <= 100, QS_EINVAL, "reps outside 1..100");
     qs_state s = nullptr;
@@ -365,6 +368,7 @@ qs_status qs_plan_time_passes(qs_plan p, qs_dtype dtype, int reps, double *us_ou
     hipEventDestroy(e1);
     qs_state_destroy(s);
     return st;
+    QS_ABI_CATCH
 }
 
 }  // extern "C"
