@@ -28,6 +28,7 @@ import math
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -410,7 +411,8 @@ def families_mode(a):
 def brickwork_mode(a):
     """28-qubit brickwork (Haar U3 on every qubit + alternating CNOT pairs,
     depth 40): complex64 and complex128, gate-by-gate vs fused (k_max 5 or
-    below, tile shape autotuned per dtype)."""
+    below, tile shape autotuned per dtype; --k-max and --tile together fix
+    the plan instead, e.g. k_max 5 to put every fused block on MFMA)."""
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
@@ -422,8 +424,11 @@ def brickwork_mode(a):
     out = {"mode": "brickwork", "n": n, "gates": len(c)}
     fused_amps = {}
     for dt, name in ((Q.QS_C64, "c64"), (Q.QS_C128, "c128")):
-        best = Q.qs_autotune(n, dt, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
-        print(f"[brickwork] {name}: autotuned k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits}",
+        if a.k_max and a.tile:
+            best = types.SimpleNamespace(k_max=a.k_max, tile_qubits=a.tile, low_qubits=a.low)
+        else:
+            best = Q.qs_autotune(n, dt, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1))
+        print(f"[brickwork] {name}: plan k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits}",
               file=sys.stderr, flush=True)
         st = Q.State(n, dt)
         plan = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,

@@ -210,6 +210,90 @@ __global__ __launch_bounds__(kThreads) void k_ctrl_c64_vec(float2 *__restrict__ 
     }
 }
 
+// complex64, control c <= 3 and target t >= 1: the control = 1 runs are at
+// most 8 amplitudes (64 bytes) long, so touching only them leaves every HBM
+// burst half used.  This variant sweeps every pair in whole 16-byte vectors
+// (2S bytes, the one-qubit sweep's pattern) and writes the control = 0 pairs
+// back unchanged.  Bit 0 of a vector's first index is 0 and bit t is 0 for a,
+// 1 for b, so for c >= 1 bit c of idx is the control of all four amplitudes;
+// for c = 0 only the second amplitude of each vector has the control set.
+__global__ __launch_bounds__(kThreads) void k_ctrl_c64_sweep(float2 *__restrict__ psi, int c, int t, uint64_t units,
+                                                             M2<float> m) {
+    const uint64_t stride = 1ull << t;
+    UNIT_LOOP(units) {
+        float4 a[kUnroll], b[kUnroll];
+        uint64_t idx[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint64_t u = base_ + j * kThreads + threadIdx.x;
+            idx[j] = ins0(u << 1, t);
+            if (u < units) {
+                a[j] = ld_nt(reinterpret_cast<const float4 *>(psi + idx[j]));
+                b[j] = ld_nt(reinterpret_cast<const float4 *>(psi + idx[j] + stride));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint64_t u = base_ + j * kThreads + threadIdx.x;
+            if (u < units) {
+                float4 x = a[j], y = b[j];
+                if (c == 0) {
+                    apply2(m, a[j].z, a[j].w, b[j].z, b[j].w, x.z, x.w, y.z, y.w);
+                } else if ((idx[j] >> c) & 1) {
+                    apply2(m, a[j].x, a[j].y, b[j].x, b[j].y, x.x, x.y, y.x, y.y);
+                    apply2(m, a[j].z, a[j].w, b[j].z, b[j].w, x.z, x.w, y.z, y.w);
+                }
+                st_nt(reinterpret_cast<float4 *>(psi + idx[j]), x);
+                st_nt(reinterpret_cast<float4 *>(psi + idx[j] + stride), y);
+            }
+        }
+    }
+}
+
+// The same sweep for targets 1 <= t <= 6: k_1q_c64_shfl's lane exchange
+// (vector u holds amplitudes 2u, 2u + 1), then the control = 0 outputs take
+// the loaded values back.  Requires units to be a multiple of 64.
+__global__ __launch_bounds__(kThreads) void k_ctrl_c64_shfl(float4 *__restrict__ psi, int c, int t, uint64_t units,
+                                                            M2<float> m) {
+    const int lx = 1 << (t - 1);
+    UNIT_LOOP(units) {
+        float4 v[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint64_t u = base_ + j * kThreads + threadIdx.x;
+            if (u < units) v[j] = ld_nt(psi + u);
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint64_t u = base_ + j * kThreads + threadIdx.x;
+            if (u < units) {  // uniform per wave
+                float4 p;
+                p.x = __shfl_xor(v[j].x, lx);
+                p.y = __shfl_xor(v[j].y, lx);
+                p.z = __shfl_xor(v[j].z, lx);
+                p.w = __shfl_xor(v[j].w, lx);
+                const bool upper = (u >> (t - 1)) & 1;  // bit t of the amplitude index
+                float4 o;
+                float dr, di;
+                if (!upper) {
+                    apply2(m, v[j].x, v[j].y, p.x, p.y, o.x, o.y, dr, di);
+                    apply2(m, v[j].z, v[j].w, p.z, p.w, o.z, o.w, dr, di);
+                } else {
+                    apply2(m, p.x, p.y, v[j].x, v[j].y, dr, di, o.x, o.y);
+                    apply2(m, p.z, p.w, v[j].z, v[j].w, dr, di, o.z, o.w);
+                }
+                if (c == 0) {
+                    o.x = v[j].x;
+                    o.y = v[j].y;
+                } else if (!(((u << 1) >> c) & 1)) {
+                    o = v[j];
+                }
+                st_nt(psi + u, o);
+            }
+        }
+    }
+}
+
 // any control/target, one pair per unit.
 template <typename R, typename A>
 __global__ __launch_bounds__(kThreads) void k_ctrl_scalar(A *__restrict__ psi, int c, int t, uint64_t units, M2<R> m) {
@@ -476,6 +560,17 @@ bool use_shuffle() {
     return v == 1;
 }
 
+// complex64 controlled gates with a low control: whole-vector sweep
+// (QS_PLAIN_CTRL_SWEEP=0: the control-half kernels)
+bool ctrl_sweep_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_PLAIN_CTRL_SWEEP");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v == 1;
+}
+
 // device copy of a dense matrix for k_dense (kept alive for the process:
 // one small cached buffer per (dtype) sized to the largest matrix seen).
 struct DenseScratch {
@@ -582,7 +677,15 @@ qs_status launch_plain(qs_state_s &s, const HGate &g) {
         prof_begin(st, QS_PROF_PLAIN, S, 14.0 * std::ldexp(1.0, n - 1));
         if (c64) {
             M2<float> m = to_m2<float>(g, 1, 3, 1, 3, 4);
-            if (c >= 1 && t >= 1) {
+            if (c <= 3 && t >= 1 && t <= 6 && n >= 7 && use_shuffle() && ctrl_sweep_enabled()) {
+                uint64_t units = 1ull << (n - 1);
+                hipLaunchKernelGGL(k_ctrl_c64_shfl, grid_for(units), dim3(kThreads), 0, st, (float4 *)s.amp, c, t,
+                                   units, m);
+            } else if (c <= 3 && t >= 1 && ctrl_sweep_enabled()) {
+                uint64_t units = 1ull << (n - 2);
+                hipLaunchKernelGGL(k_ctrl_c64_sweep, grid_for(units), dim3(kThreads), 0, st, (float2 *)s.amp, c, t,
+                                   units, m);
+            } else if (c >= 1 && t >= 1) {
                 uint64_t units = 1ull << (n - 3);
                 hipLaunchKernelGGL(k_ctrl_c64_vec, grid_for(units), dim3(kThreads), 0, st, (float2 *)s.amp, c, t,
                                    units, m);

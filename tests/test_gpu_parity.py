@@ -92,6 +92,24 @@ def test_plain_every_kind_every_qubit(Q, oracle, dtype, tol, n):
 
 
 @pytest.mark.parametrize("dtype,tol", [(0, TOL64), (1, TOL128)])
+def test_plain_low_controls_18q(Q, oracle, dtype, tol):
+    # controls 0..3 against every target: the whole-vector sweep of the
+    # complex64 controlled kernels, over many workgroups and grid strides
+    n = 18
+    rng = np.random.default_rng(7)
+    c = qsynth.Circuit(n)
+    for ctl in range(4):
+        for tgt in range(n):
+            if tgt != ctl:
+                for name in qsynth.TWO_QUBIT:
+                    c.add(name, (ctl, tgt), tuple(rng.random() * 6 for _ in range(qsynth.N_PARAMS.get(name, 0))))
+    psi0 = qsynth.random_state(n, seed=5)
+    ref = oracle.run(c, psi0.copy())
+    got = run_plain(Q, c, dtype, psi0)
+    assert oracle.max_abs(ref, got) <= tol * max(1, len(c) / 100)
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL64), (1, TOL128)])
 def test_plain_dense_gates(Q, oracle, dtype, tol):
     n = 8
     c = qsynth.random_circuit(n, 40, seed=3, kinds=["h", "cx"], max_dense=5 if dtype == 1 else 6)
