@@ -94,6 +94,12 @@ constexpr int tile_waves() {
     return WIDE ? 1 : (sizeof(R) == 4 && NJ > 0 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
 }
 
+// LDS of a tile pass.  Unstaged variants of a fixed tile size hold the tile
+// and the per-wave norm slots in static LDS and take no dynamic LDS.  The
+// others declare no static LDS; their dynamic region is the tile (2^t
+// amplitudes), the norm slots, then the staged block operands.
+constexpr size_t kRedBytes = 128;   // NT / 64 doubles for up to 1024 threads
+
 template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
 __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_tile_pass(
     typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
@@ -105,10 +111,27 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     constexpr int PF = NJ > 0 ? (NJ < PFMAX ? NJ : PFMAX) : kPrefetch;
     constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    A *tile = reinterpret_cast<A *>(smem_raw);
-    __shared__ double red[NT / 64];
+    static_assert(NT / 64 * sizeof(double) <= kRedBytes, "norm slots");
     const int T = pa.t;
     const uint32_t tsize = 1u << T;
+    A *tile;
+    double *red;
+    R *cst;
+    if constexpr (NJ > 0 && !CL) {
+        // fixed tile size, no staged operands: tile and norm slots in static
+        // LDS, whose addresses are constants the compiler folds into every
+        // access (the staged variants keep the dynamic layout: with a static
+        // tile their register allocation spills)
+        __shared__ __align__(16) A tile_s[NJ * NT * APV];
+        __shared__ double red_s[NT / 64];
+        tile = tile_s;
+        red = red_s;
+        cst = reinterpret_cast<R *>(smem_raw);
+    } else {
+        tile = reinterpret_cast<A *>(smem_raw);
+        red = reinterpret_cast<double *>(smem_raw + (size_t)tsize * sizeof(A));
+        cst = reinterpret_cast<R *>(smem_raw + (size_t)tsize * sizeof(A) + kRedBytes);
+    }
     const R sc = pa.apply_scale ? (R)(*scale_in) : (R)1;
     const uint32_t my_li = threadIdx.x * APV;
     const bool active = NJ > 0 || my_li < tsize;   // small tiles: fewer vectors than threads
@@ -144,7 +167,6 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     double wg_norm = 0.0;   // thread 0: this workgroup's tiles, in tile order
     // block operands of the pass -> LDS behind the tile (once per workgroup;
     // pool entries are 16-byte aligned and cl_len a multiple of 16 bytes)
-    R *cst = reinterpret_cast<R *>(smem_raw + (size_t)tsize * sizeof(A));
     if constexpr (CL) {
         constexpr int EPV = 16 / sizeof(R);
         for (int i = threadIdx.x * EPV; i < pa.cl_len; i += NT * EPV)
@@ -295,14 +317,16 @@ using TileKernel = void (*)(typename AmpOf<R>::A *, uint64_t, PassArgs, const Bl
 // Kernel variant for a pass: register footprint (wide), LDS-staged operands
 // (cl) and, for the narrow variant, the compile-time vector count.
 template <typename R>
-TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
+TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads, bool &static_tile) {
     constexpr int APV = sizeof(R) == 4 ? 2 : 1;
     const int vpt = (1 << t) / (TT * APV);   // 16-byte vectors per thread
     threads = TT;
+    static_tile = false;
     if (wide) return k_tile_pass<R, true, 0, false>;
     if constexpr (sizeof(R) == 4) {
         // unstaged 2^13 / 2^14 tiles: more threads per workgroup, 8 vectors each
         if (!cl && big_tiles_enabled()) {
+            static_tile = t == 13 || t == 14;
             if (t == 13) {
                 threads = 512;
                 return k_tile_pass<R, false, 8, false, 512>;
@@ -329,6 +353,7 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
                 if (vpt == 16) return k_tile_pass<R, false, 16, true>;
             }
         }
+        static_tile = vpt == 1 || vpt == 2 || vpt == 4 || vpt == 8 || vpt == 16;
         if (vpt == 1) return k_tile_pass<R, false, 1, false>;
         if (vpt == 2) return k_tile_pass<R, false, 2, false>;
         if (vpt == 4) return k_tile_pass<R, false, 4, false>;
@@ -341,7 +366,7 @@ TileKernel<R> pick_tile_kernel(bool wide, int t, bool cl, int &threads) {
 // LDS bytes a pass may use for staged operands: what is left of the CU's LDS
 // share per workgroup at the occupancy the staged variant targets (complex64
 // 2^11: 4, 2^12: 3, 2^13: 2 workgroups per CU; complex128 2^11, 2^12: 2),
-// minus the tile and a margin for the kernel's static LDS.  0 = no staged
+// minus the tile and a margin that holds the norm slots.  0 = no staged
 // variant for this tile.
 size_t lds_operand_budget(int t, qs_dtype dt) {
     constexpr size_t kLds = 160 * 1024, kMargin = 512;
@@ -973,12 +998,14 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     // loads in flight while the current one is processed
     const bool wide = p.pass_wide[di][pass_index] != 0;
     const size_t amp = s.dtype == QS_C64 ? 8 : 16;
-    const size_t lds = (amp << ps.t) + (size_t)pa.cl_len * (s.dtype == QS_C64 ? 4 : 8);
     int threads = TT;
+    bool static_tile = false;
     TileKernel<float> k32 = nullptr;
     TileKernel<double> k64 = nullptr;
-    if (s.dtype == QS_C64) k32 = pick_tile_kernel<float>(wide, ps.t, cl, threads);
-    else k64 = pick_tile_kernel<double>(wide, ps.t, cl, threads);
+    if (s.dtype == QS_C64) k32 = pick_tile_kernel<float>(wide, ps.t, cl, threads, static_tile);
+    else k64 = pick_tile_kernel<double>(wide, ps.t, cl, threads, static_tile);
+    // dynamic LDS: none for the static-tile variants, else tile + norm slots + staged operands
+    const size_t lds = static_tile ? 0 : (amp << ps.t) + kRedBytes + (size_t)pa.cl_len * (s.dtype == QS_C64 ? 4 : 8);
     const void *fn = k32 ? reinterpret_cast<const void *>(k32) : reinterpret_cast<const void *>(k64);
     const uint64_t resident = resident_groups(fn, threads, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
