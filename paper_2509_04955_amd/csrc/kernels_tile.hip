@@ -235,15 +235,17 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) nacc += __shfl_xor(nacc, o);
             red[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)] = nacc;   // every lane holds the wave sum
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double s = 0;
-#pragma unroll
-                for (int w = 0; w < NT / 64; ++w) s += red[w];
-                wg_norm += s;
-            }
         }
-        __syncthreads();  // every read of this tile from LDS is done
+        __syncthreads();  // every read of this tile from LDS is done, every norm slot written
+        // Thread 0 sums the slots after that barrier; they are written again
+        // only in the next tile's store phase, behind the loop-top barrier
+        // that wave 0 reaches after these reads.
+        if (pa.want_norm && threadIdx.x == 0) {
+            double s = 0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) s += red[w];
+            wg_norm += s;
+        }
         if (!more) break;
         if (active) {
 #pragma unroll
