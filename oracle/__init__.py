@@ -7,15 +7,15 @@ share only the seeded input generators in ``qsynth``.
 
 What it computes is the plain definition of circuit simulation (paper,
 Section 2.1, Eq. 1-4): the output state is U_G ... U_1 psi_in, each gate
-applied to the whole amplitude array in program order (Algorithms 1 and 2),
+applied to the whole amplitude array in program order (Eq. 3 and Eq. 4),
 in complex128.  Gate contraction, tiling and passes of the fast path reach
 the same result (up to rounding) faster, so this plain form is what the fast
 path is compared with.
 
 Parts:
   * ``sv_oracle.c`` (compiled with gcc): gate loops, dense k-qubit gates,
-    norm, Pauli expectation, closed-form Pauli rotation, loop-form index
-    enumerations, the operation-count model.
+    norm, Pauli expectation, closed-form Pauli rotation, the pair index set
+    of Eq. 3/4, the operation-count model.
   * ``brute.py``: 2^n x 2^n Kronecker matrices (n <= 10), gates defined from
     their generators with a matrix exponential.
   * ``greedy.py``: the fixed-width greedy contraction rule and the plan
@@ -83,14 +83,8 @@ def lib():
         L.or_expect_pauli_sum.argtypes = [c_dp, ctypes.c_int, c_dp, c_dp, c_dp, ctypes.c_int]
         L.or_expect_pauli_sum.restype = ctypes.c_double
         L.or_pauli_rotation.argtypes = [c_dp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double]
-        for nm in ("or_pairs_alg1", "or_pairs_alg3"):
-            f = getattr(L, nm)
-            f.argtypes = [ctypes.c_int, ctypes.c_int, c_dp, ctypes.c_int64]
-            f.restype = ctypes.c_int64
-        for nm in ("or_pairs_alg2", "or_pairs_alg4"):
-            f = getattr(L, nm)
-            f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, c_dp, ctypes.c_int64]
-            f.restype = ctypes.c_int64
+        L.or_pair_lows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, c_dp, ctypes.c_int64]
+        L.or_pair_lows.restype = ctypes.c_int64
         L.or_opcount.argtypes = [ctypes.c_int, ctypes.c_int]
         L.or_opcount.restype = ctypes.c_double
         _lib = L
@@ -137,8 +131,8 @@ def gate_2x2(name: str, params=()) -> np.ndarray:
 
 
 def apply_gate(psi: np.ndarray, n: int, name: str, qubits, params=(), matrix=None) -> None:
-    """Apply one gate in place (Algorithm 1 for one-qubit kinds, Algorithm 2
-    for controlled kinds with qubits = (control, target), the dense routine
+    """Apply one gate in place (the pair update of Eq. 3 for one-qubit kinds,
+    Eq. 4 for controlled kinds with qubits = (control, target), the dense routine
     for 'dense' with local bit j <-> qubits[j])."""
     assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.size == 1 << n
     q = np.asarray(qubits, dtype=np.int32)
@@ -194,15 +188,18 @@ def pauli_rotation(psi: np.ndarray, n: int, x: int, z: int, theta: float) -> Non
     lib().or_pauli_rotation(_ptr(psi), n, int(x), int(z), float(theta))
 
 
-def pairs(alg: int, n: int, a: int, b: int | None = None) -> np.ndarray:
-    """Lower pair indices visited by Algorithm `alg` (1-4) of Section 2.2."""
+def pair_lows(n: int, t: int, controls=()) -> np.ndarray:
+    """Lower members of the amplitude pairs a gate on target t couples
+    (Eq. 3; with controls, Eq. 4): every i with bit t clear and all control
+    bits set, in increasing order.  Pinned against brute-force set-builder
+    enumeration and the grouped traversal of Section 2.2 in
+    tests/test_oracle_pins.py."""
     cap = 1 << n
     out = np.zeros(cap, dtype=np.int64)
-    L = lib()
-    if alg in (1, 3):
-        cnt = getattr(L, f"or_pairs_alg{alg}")(n, a, _ptr(out), cap)
-    else:
-        cnt = getattr(L, f"or_pairs_alg{alg}")(n, a, b, _ptr(out), cap)
+    cm = 0
+    for c in controls:
+        cm |= 1 << int(c)
+    cnt = lib().or_pair_lows(n, t, cm, _ptr(out), cap)
     return out[: min(cnt, cap)].copy()
 
 
@@ -213,7 +210,10 @@ def opcount(n: int, k: int) -> float:
 
 
 def fidelity(ref: np.ndarray, got: np.ndarray) -> float:
-    """|<ref|got>|^2 / (|ref|^2 |got|^2), accumulated in FP64."""
+    """|<ref|got>|^2 / (<ref|ref> <got|got>), accumulated in FP64: 1 for equal
+    states up to a global phase and scale, 0 for orthogonal ones.  Pinned in
+    tests/test_oracle_metrics.py (orthogonal states, |0> against |+>, phase
+    and scale invariance, a hand-computed overlap)."""
     ref = np.asarray(ref, dtype=np.complex128)
     got = np.asarray(got, dtype=np.complex128)
     ov = np.vdot(ref, got)
@@ -221,4 +221,6 @@ def fidelity(ref: np.ndarray, got: np.ndarray) -> float:
 
 
 def max_abs(ref: np.ndarray, got: np.ndarray) -> float:
+    """max_i |got[i] - ref[i]| in FP64, no phase alignment or normalisation.
+    Pinned in tests/test_oracle_metrics.py (hand-computed cases)."""
     return float(np.max(np.abs(np.asarray(ref, dtype=np.complex128) - np.asarray(got, dtype=np.complex128))))

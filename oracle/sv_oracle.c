@@ -104,44 +104,52 @@ int or_gate_2x2(int kind, const double *p, cplx *m)
 }
 
 /* ------------------------------------------------------------------ */
-/* Single-qubit gate: Algorithm 1 (Section 2.2) and Eq. 3.              */
-/* For every index i whose bit k is 0, the pair (i, i + 2^k) is         */
-/* replaced by U applied to it.                                         */
+/* Index helper: the m-th index (in increasing order) whose bit p is 0,  */
+/* i.e. m with a zero bit inserted at position p.                        */
+/* ------------------------------------------------------------------ */
+static int64_t with_zero_bit(int64_t m, int p)
+{
+    const int64_t low = m & (((int64_t)1 << p) - 1);
+    return ((m - low) << 1) | low;
+}
+
+/* ------------------------------------------------------------------ */
+/* Single-qubit gate, Eq. 3 (Section 2.2): U on qubit k couples exactly  */
+/* the amplitude pairs (i, i + 2^k) with bit k of i equal to 0; every    */
+/* such pair is replaced by U applied to it.  The 2^(n-1) lower members  */
+/* are enumerated directly as m with a zero bit inserted at k.           */
 /* ------------------------------------------------------------------ */
 void or_apply_1q(cplx *psi, int n, int k, const cplx *u)
 {
-    const int64_t dim = (int64_t)1 << n;
-    const int64_t mask = (int64_t)1 << k;
+    const int64_t npairs = (int64_t)1 << (n - 1);
+    const int64_t step = (int64_t)1 << k;
     #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < dim; ++i) {
-        if ((i & mask) == 0) {
-            cplx a0 = psi[i];
-            cplx a1 = psi[i + mask];
-            psi[i] = u[0] * a0 + u[1] * a1;
-            psi[i + mask] = u[2] * a0 + u[3] * a1;
-        }
+    for (int64_t m = 0; m < npairs; ++m) {
+        const int64_t lo = with_zero_bit(m, k), hi = lo + step;
+        const cplx a0 = psi[lo], a1 = psi[hi];
+        psi[lo] = u[0] * a0 + u[1] * a1;
+        psi[hi] = u[2] * a0 + u[3] * a1;
     }
 }
 
 /* ------------------------------------------------------------------ */
-/* Controlled gate: Algorithm 2 (Section 2.2) and Eq. 4, with the       */
-/* control condition generalised to a mask of control bits (all must    */
-/* be 1).  Indices whose control bits are not all 1 are skipped.        */
+/* Controlled gate, Eq. 4 (Section 2.1): |0><0| (x) I + |1><1| (x) U on  */
+/* (control, target), generalised to a set of control bits.  The pairs   */
+/* it couples are the target pairs of Eq. 3 restricted to the set        */
+/* { i : (i & ctrl_mask) == ctrl_mask }; the others are left unchanged.  */
 /* ------------------------------------------------------------------ */
 void or_apply_controlled(cplx *psi, int n, uint64_t ctrl_mask, int t, const cplx *u)
 {
-    const int64_t dim = (int64_t)1 << n;
-    const int64_t mt = (int64_t)1 << t;
-    const int64_t mc = (int64_t)ctrl_mask;
+    const int64_t npairs = (int64_t)1 << (n - 1);
+    const int64_t step = (int64_t)1 << t;
+    const int64_t cm = (int64_t)ctrl_mask;
     #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < dim; ++i) {
-        if ((i & mc) != mc) continue;
-        if ((i & mt) == 0) {
-            cplx a0 = psi[i];
-            cplx a1 = psi[i + mt];
-            psi[i] = u[0] * a0 + u[1] * a1;
-            psi[i + mt] = u[2] * a0 + u[3] * a1;
-        }
+    for (int64_t m = 0; m < npairs; ++m) {
+        const int64_t lo = with_zero_bit(m, t), hi = lo + step;
+        if ((lo & cm) != cm) continue;
+        const cplx a0 = psi[lo], a1 = psi[hi];
+        psi[lo] = u[0] * a0 + u[1] * a1;
+        psi[hi] = u[2] * a0 + u[3] * a1;
     }
 }
 
@@ -356,49 +364,22 @@ void or_pauli_rotation(cplx *psi, int n, uint64_t x, uint64_t z, double theta)
 }
 
 /* ------------------------------------------------------------------ */
-/* Index enumerations used to check the paper's loop forms against each */
-/* other.  Each writes the lower index of every visited pair into out   */
-/* (capacity cap) and returns the count.                                */
+/* The lower members of the pairs a gate on target t couples, from the  */
+/* definitions of Eq. 3 and Eq. 4: { i : bit t of i is 0 and            */
+/* (i & ctrl_mask) == ctrl_mask }, in increasing order (ctrl_mask = 0:  */
+/* a one-qubit gate).  Written to out (capacity cap); returns the count. */
+/* Tests compare this set with the grouped traversal of Section 2.2.    */
 /* ------------------------------------------------------------------ */
-/* Algorithm 1: scan all i, keep those with bit k clear. */
-int64_t or_pairs_alg1(int n, int k, int64_t *out, int64_t cap)
+int64_t or_pair_lows(int n, int t, uint64_t ctrl_mask, int64_t *out, int64_t cap)
 {
-    int64_t cnt = 0, mask = (int64_t)1 << k;
-    for (int64_t i = 0; i < ((int64_t)1 << n); ++i)
-        if ((i & mask) == 0) { if (cnt < cap) out[cnt] = i; ++cnt; }
-    return cnt;
-}
-
-/* Algorithm 3: groups of 2^(k+1), first half of each group. */
-int64_t or_pairs_alg3(int n, int k, int64_t *out, int64_t cap)
-{
-    int64_t cnt = 0, mask = (int64_t)1 << k, gs = (int64_t)1 << (k + 1);
-    for (int64_t g = 0; g < ((int64_t)1 << n); g += gs)
-        for (int64_t i = g; i < g + mask; ++i) { if (cnt < cap) out[cnt] = i; ++cnt; }
-    return cnt;
-}
-
-/* Algorithm 2: scan all i, keep control bit set and target bit clear. */
-int64_t or_pairs_alg2(int n, int c, int t, int64_t *out, int64_t cap)
-{
-    int64_t cnt = 0, mc = (int64_t)1 << c, mt = (int64_t)1 << t;
-    for (int64_t i = 0; i < ((int64_t)1 << n); ++i) {
-        if ((i & mc) == 0) continue;
-        if ((i & mt) == 0) { if (cnt < cap) out[cnt] = i; ++cnt; }
+    int64_t cnt = 0;
+    const int64_t cm = (int64_t)ctrl_mask;
+    for (int64_t m = 0; m < ((int64_t)1 << (n - 1)); ++m) {
+        const int64_t lo = with_zero_bit(m, t);
+        if ((lo & cm) != cm) continue;
+        if (cnt < cap) out[cnt] = lo;
+        ++cnt;
     }
-    return cnt;
-}
-
-/* Algorithm 4 (grouped controlled loop).  As printed, the middle loop
- * walks s from g + 2^c to g + 2^t - 1 in steps of 2^(c+1); that enumerates
- * exactly the control-set / target-clear indices only when c < t. */
-int64_t or_pairs_alg4(int n, int c, int t, int64_t *out, int64_t cap)
-{
-    int64_t cnt = 0, mc = (int64_t)1 << c, mt = (int64_t)1 << t;
-    int64_t gsc = (int64_t)1 << (c + 1), gst = (int64_t)1 << (t + 1);
-    for (int64_t g = 0; g < ((int64_t)1 << n); g += gst)
-        for (int64_t s = g + mc; s <= g + mt - 1; s += gsc)
-            for (int64_t i = s; i < s + mc; ++i) { if (cnt < cap) out[cnt] = i; ++cnt; }
     return cnt;
 }
 

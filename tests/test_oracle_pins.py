@@ -117,28 +117,35 @@ def test_random_circuits_vs_brute(oracle, seed):
     assert np.max(np.abs(got - ref)) < 1e-12
 
 
-def test_algorithm_index_sets(oracle):
-    """Algorithms 1 and 3 visit the same pairs; Algorithms 2 and 4 do too
-    when c < t.  For c > t the printed Algorithm 4 loop visits a different
-    set, which is why the controlled loop is implemented by bit tests."""
+def test_pair_index_sets(oracle):
+    """The pairs a gate couples (Eq. 3, Eq. 4) against two other descriptions
+    of the same set: a brute-force scan of all indices by their bits, and the
+    grouped traversal of Section 2.2, where the index space is cut into
+    groups of 2^(t+1) whose first half holds the lower members (for a control
+    c < t, each half is cut again into runs of 2^c with the control bit in the
+    odd runs).  The grouped form is written here as a reshape of the index
+    array: group, half, run, parity of the run, position in the run."""
     n = 7
-    for k in range(n):
-        a1, a3 = oracle.pairs(1, n, k), oracle.pairs(3, n, k)
-        assert len(a1) == 1 << (n - 1)
-        assert np.array_equal(np.sort(a1), np.sort(a3))
-    mismatched = 0
+    idx = np.arange(1 << n)
+    for t in range(n):
+        got = oracle.pair_lows(n, t)
+        assert len(got) == 1 << (n - 1)
+        assert np.array_equal(got, idx[(idx >> t) & 1 == 0])
+        grouped = idx.reshape(-1, 2, 1 << t)[:, 0, :].ravel()
+        assert np.array_equal(got, grouped)
     for c in range(n):
         for t in range(n):
             if c == t:
                 continue
-            a2, a4 = oracle.pairs(2, n, c, t), oracle.pairs(4, n, c, t)
-            assert len(a2) == 1 << (n - 2)
-            same = len(a4) == len(a2) and np.array_equal(np.sort(a2), np.sort(a4))
+            got = oracle.pair_lows(n, t, (c,))
+            assert len(got) == 1 << (n - 2)
+            assert np.array_equal(got, idx[((idx >> t) & 1 == 0) & ((idx >> c) & 1 == 1)])
             if c < t:
-                assert same
-            else:
-                mismatched += not same
-    assert mismatched > 0
+                grouped = idx.reshape(-1, 2, 1 << (t - c - 1), 2, 1 << c)[:, 0, :, 1, :].ravel()
+                assert np.array_equal(got, grouped)
+    # two controls: both bits set
+    got = oracle.pair_lows(n, 3, (0, 5))
+    assert np.array_equal(got, idx[((idx >> 3) & 1 == 0) & ((idx & 0b100001) == 0b100001)])
 
 
 def test_kronecker_fusion_printed_entries(oracle):
