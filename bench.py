@@ -11,14 +11,16 @@ and run the whole contracted circuit (every tile pass with its FP64
 renormalisation); the contraction plan (host) is built once before timing and
 its time is reported separately.
 
-Prints one JSON line.  `value` is the effective bandwidth of the fused
-circuit: the bytes the gate-by-gate method must stream for the same circuit
-(per gate 2S for a general or diagonal 1-qubit gate, S for a phase gate,
-CNOT-type or SWAP, S/2 for CZ-type; S = state bytes) divided by the circuit
-time.  The plain method's own effective bandwidth uses the same numerator, so
-the ratio of the two is the speedup.  `streamed_gbs` is what the fused passes
-actually move, (passes * 2 * S + S) / step time, and `roofline` is the tile
-kernel against the HBM (or MFMA) peak.
+Prints one JSON line.  `value` is the bandwidth of the fused circuit by the
+algorithmic bytes of the method that ran: each tile pass reads and writes the
+state once (2S, S = state bytes), plus the reset of the state to |0...0> at
+the start of a step (one write, S), divided by the circuit time.  `gate_by_gate_equivalent` states what the plain
+gate-by-gate method would have to stream for the same circuit (per gate 2S for
+a general or diagonal 1-qubit gate, S for a phase gate, CNOT-type or SWAP,
+S/2 for CZ-type) and that volume over the fused time: a speed measure, not an
+HBM rate.  `roofline` is the tile kernel against the HBM (or MFMA) peak, and
+`accuracy` runs the circuit's inverse after the timed steps (exact result
+|0...0>) and states the round trip's error.
 """
 from __future__ import annotations
 
@@ -167,8 +169,8 @@ def batch_mode(a):
     gbb = sum(plain_bytes(c, 8 << c.n) for c in circuits)
     out = {"mode": "batch", "states": a.states, "ms_per_batch": round(ms, 3),
            "states_per_s": round(a.states / (ms / 1e3), 1), "amplitudes": amps,
-           "circuits_effective_gbs": round(gbb / (ms * 1e-3) / 1e9, 1),
-           "note": "effective = the circuits' gate-by-gate bytes / batch time; the states are MALL-resident "
+           "circuits_gate_by_gate_equivalent_gbs": round(gbb / (ms * 1e-3) / 1e9, 1),
+           "note": "the circuits' gate-by-gate bytes / batch time (a speed measure); the states are MALL-resident "
                    "(cache-resident, not an HBM fraction)",
            "gates": sum(len(c) for c in circuits), "terms": sum(len(h) for h in hams),
            "create_s": round(create_s, 2), "energy_mean": float(np.mean(E))}
@@ -403,7 +405,7 @@ def families_mode(a):
                          "speedup": round(ms_plain / ms_fused, 2),
                          "rotation_passes": int(rinfo.n_passes), "rotation_ms": round(ms_rot, 2),
                          "rotation_speedup": round(ms_plain / ms_rot, 2),
-                         "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1)})
+                         "fused_gate_by_gate_equivalent_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1)})
             print(f"[families] {rows[-1]}", file=sys.stderr, flush=True)
     print(json.dumps({"mode": "families", "rows": rows}), flush=True)
 
@@ -441,11 +443,18 @@ def brickwork_mode(a):
                      "speedup": round(ms_plain / ms_fused, 2), "passes": int(info.n_passes),
                      "k_max": best.k_max, "tile_qubits": best.tile_qubits, "low_qubits": best.low_qubits,
                      "plain_effective_gbs": round(plain_bytes(c, S) / (ms_plain * 1e-3) / 1e9, 1),
-                     "fused_effective_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1),
+                     "fused_gate_by_gate_equivalent_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1),
                      "fused_streamed_gbs": round((info.n_passes * 2 + 1) * S / (ms_fused * 1e-3) / 1e9, 1)}
         st.set_basis(0)
         st.apply_plan(plan)
         fused_amps[name] = st.amplitudes()
+        # round trip through the inverse circuit (exact result |0...0>)
+        inv = Q.qs_contract(n, Q.GateList(qsynth.inverse(c)), Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
+                                                                    low_qubits=best.low_qubits, dtype=dt))
+        rt_inf, rt_max = roundtrip_error(Q, st, inv)
+        Q.qs_plan_destroy(inv)
+        out[name]["accuracy"] = {"check": "circuit then its inverse from |0...0> (exact result |0...0>)",
+                                 "one_minus_fidelity": rt_inf, "max_abs": rt_max}
         st.close()
         Q.qs_plan_destroy(plan)
     # complex64 against the complex128 result (held to 1e-12 of the FP64 oracle by the parity tests)
@@ -471,6 +480,23 @@ def brickwork_mode(a):
                            "sample": f"first {k} of {len(c)} gates at n={n}, FP64 gate-by-gate ({cpu_s:.1f} s), "
                                      "extrapolated linearly"}
     print(json.dumps(out), flush=True)
+
+
+def roundtrip_error(Q, st, plan_inv):
+    """Apply the inverse circuit's plan to the state the timed steps left and
+    compare with the exact result |0...0>: (1 - |<0|psi>|^2 / <psi|psi>,
+    max_i |psi_i - delta_i0|) after the pending FP64 renormalisation is
+    applied to the amplitudes."""
+    import torch
+
+    st.apply_plan(plan_inv)
+    Q.qs_state_normalize(st.handle)
+    torch.cuda.synchronize()
+    t = st.tensor
+    a0 = complex(t[0].item())
+    nrm = st.norm()
+    rest = float(t[1:].abs().max().item()) if t.numel() > 1 else 0.0
+    return 1.0 - abs(a0) ** 2 / nrm, max(abs(a0 - 1.0), rest)
 
 
 def pauli_contraction(a, Q, n, circ, gl, st_greedy, S, greedy_ms, stream):
@@ -526,13 +552,23 @@ def pauli_contraction(a, Q, n, circ, gl, st_greedy, S, greedy_ms, stream):
         n2 += float(np.vdot(ap, ap).real)
     fid = float(abs(dot) ** 2 / (n1 * n2))
     progress(f"fidelity vs greedy {fid:.12f}")
+    import qsynth
+
+    inv = Q.qs_contract(n, Q.GateList(qsynth.inverse(circ)),
+                        Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits, low_qubits=best.low_qubits,
+                               strategy=Q.STRATEGY_PAULI, renorm=1))
+    rt_inf, rt_max = roundtrip_error(Q, st, inv)
+    progress(f"circuit + inverse: 1 - F = {rt_inf:.3e}, max-abs {rt_max:.3e}")
+    Q.qs_plan_destroy(inv)
     st.close()
     Q.qs_plan_destroy(plan)
     return {"strategy": Q.STRATEGY_PAULI, "k_max": best.k_max, "tile_qubits": best.tile_qubits,
             "low_qubits": best.low_qubits, "n_blocks": int(info.n_blocks), "n_passes": int(info.n_passes),
             "circuit_time_s": round(ms / 1e3, 4), "speedup_vs_greedy": round(greedy_ms / ms, 3),
-            "effective_gbs": round(plain_bytes(circ, S) / (ms * 1e-3) / 1e9, 1),
             "streamed_gbs": round((info.n_passes * 2 * S + S) / (ms * 1e-3) / 1e9, 1),
+            "gate_by_gate_equivalent_gbs": round(plain_bytes(circ, S) / (ms * 1e-3) / 1e9, 1),
+            "accuracy": {"check": "circuit then its inverse from |0...0> (exact result |0...0>)",
+                         "one_minus_fidelity": rt_inf, "max_abs": rt_max},
             "tile_pass_ms": round(tile_ms, 4), "tile_pass_frac_of_8tbs": round(2 * S / (tile_ms * 1e-3) / 8e12, 4),
             "plan_time_s": round(plan_s, 3), "autotune_s": round(tune_s, 2), "fidelity_vs_greedy": fid,
             "note": "runs of gates equal to one Pauli rotation contracted into one block each (beyond the "
@@ -600,9 +636,10 @@ def main():
     prof = Q.qs_profile_collect()
     Q.qs_profile_enable(False)
     ms_step = total_ms / a.steps
+    # algorithmic bytes of one step: the reset of the state (S) and 2S per tile pass
     alg_bytes = info.n_passes * 2 * S + S
-    streamed = alg_bytes / (ms_step * 1e-3) / 1e9
-    value = plain_bytes(circ, S) / (ms_step * 1e-3) / 1e9
+    value = alg_bytes / (ms_step * 1e-3) / 1e9
+    gbg_bytes = plain_bytes(circ, S)
     nrm = st.norm()
 
     # dominant kernel: tile pass (per-launch averages from HIP events)
@@ -635,8 +672,12 @@ def main():
                    "k_max": a.k_max, "tile_qubits": a.tile, "low_qubits": a.low, "strategy": a.strategy,
                    "flops_per_amp_dense_equiv": round(info.flops_per_amp / max(1, info.n_passes), 1)},
         "circuit_time_s": round(ms_step / 1e3, 4),
-        "streamed_gbs": round(streamed, 1),
         "gates_per_s": round(info.n_gates / (ms_step / 1e3), 1),
+        "gate_by_gate_equivalent": {
+            "bytes_per_circuit": gbg_bytes,
+            "rate_gbs": round(gbg_bytes / (ms_step * 1e-3) / 1e9, 1),
+            "note": "bytes the gate-by-gate method must stream for this circuit / fused circuit time: a speed "
+                    "measure (the plain method at the same rate would match the fused time), not an HBM rate"},
         "plan_time_s": round(plan_s, 3),
         "autotune_s": round(tune_s, 2),
         "norm_after": nrm,
@@ -661,6 +702,17 @@ def main():
     # ---- the same circuit with Pauli-rotation contraction (beside the paper's rule) ----
     if a.pauli and a.strategy == Q.STRATEGY_GREEDY:
         out["pauli_contraction"] = pauli_contraction(a, Q, n, circ, gl, st, S, ms_step, stream)
+
+    # ---- accuracy: the inverse circuit after the timed steps returns |0...0> exactly ----
+    inv = Q.qs_contract(n, Q.GateList(qsynth.inverse(circ)),
+                        Q.opts(k_max=a.k_max, tile_qubits=a.tile, low_qubits=a.low, strategy=a.strategy, renorm=1))
+    rt_inf, rt_max = roundtrip_error(Q, st, inv)
+    Q.qs_plan_destroy(inv)
+    out["accuracy"] = {"check": "circuit then its inverse from |0...0> in the same plan configuration; the exact "
+                                "(FP64) result is |0...0>",
+                       "one_minus_fidelity": rt_inf, "max_abs": rt_max,
+                       "note": "whole-circuit error against the FP64 oracle at 22 qubits: tests/test_gpu_accuracy.py"}
+    print(f"[accuracy] circuit + inverse: 1 - F = {rt_inf:.3e}, max-abs {rt_max:.3e}", file=sys.stderr, flush=True)
 
     # ---- fused vs gate-by-gate on a prefix of the same circuit ----
     if a.plain_prefix > 0:
@@ -699,7 +751,7 @@ def main():
             "plain_gates_per_s": round(info2.n_gates / (plain_ms / 1e3), 1),
             "plain_effective_gbs": round(pp.bytes[Q.PROF_PLAIN] / (pp.ms[Q.PROF_PLAIN] * 1e-3) / 1e9, 1)
             if pp.ms[Q.PROF_PLAIN] > 0 else None,
-            "fused_effective_gbs": round(plain_bytes(pre_gates, S) / (fused_ms * 1e-3) / 1e9, 1),
+            "fused_gate_by_gate_equivalent_gbs": round(plain_bytes(pre_gates, S) / (fused_ms * 1e-3) / 1e9, 1),
             # the byte table above against the library's own count for the prefix
             "plain_bytes_table_vs_library": round(plain_bytes(pre_gates, S) / max(1.0, pp.bytes[Q.PROF_PLAIN]), 6),
             "plain_extrapolated_circuit_s": round(plain_ms / 1e3 * info.n_gates / info2.n_gates, 2),
@@ -724,11 +776,13 @@ def main():
         per_gate = cpu_s / len(gates)
         cpu_circuit_s = per_gate * info.n_gates
         out["cpu_baseline"] = {
-            "value": round(plain_bytes(circ, S) / cpu_circuit_s / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "value": round(plain_bytes(circ, 2 * S) / cpu_circuit_s / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {len(gates)} gates of the same circuit at n={n}, FP64 gate-by-gate "
                       f"({cpu_s:.1f} s); extrapolated linearly to {info.n_gates} gates = {cpu_circuit_s:.0f} s; "
-                      "value = the circuit's gate-by-gate bytes / extrapolated oracle time",
+                      "value = the algorithmic bytes of the method the oracle runs (gate by gate on a complex128 "
+                      "state) / extrapolated oracle time",
+            "circuit_time_s_extrapolated": round(cpu_circuit_s, 1),
             "gates_per_s": round(1.0 / per_gate, 3),
         }
     print(json.dumps(out), flush=True)

@@ -21,7 +21,11 @@
  *     batch).  Functions that return host values synchronise that stream.
  *   - All compute runs in the library's HIP kernels; there is no CPU
  *     fallback.  Without a usable gfx950 device the device calls return
- *     QS_EDEVICE.  Host-only calls (qs_contract, qs_plan_*) work anywhere.
+ *     QS_EDEVICE.  Host-only calls (qs_contract, qs_plan_*) work anywhere,
+ *     except qs_contract with QS_STRATEGY_LEARNED and a loaded cost model:
+ *     it runs the model's inference kernel, so it needs the device that
+ *     holds the model (without a model that strategy is plain greedy and
+ *     stays host-only).
  */
 #ifndef QSIM_H
 #define QSIM_H

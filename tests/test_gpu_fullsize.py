@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size: 30-qubit states in the launch
-configuration the bench times for the UCC workload (k_max 4, 2^12-amplitude
-tiles with 4 fixed low qubits, block operands staged in LDS), checked on
+configuration the bench times for the UCC workload (k_max 4, 2^13-amplitude
+tiles with 4 fixed low qubits, 512-thread workgroups), checked on
 outputs an oracle computes one amplitude at a time and on properties that
 hold at any size.
 
@@ -20,7 +20,7 @@ import pytest
 import qsynth
 
 N = 30
-BENCH = dict(k_max=4, tile_qubits=12, low_qubits=4)
+BENCH = dict(k_max=4, tile_qubits=13, low_qubits=4)
 
 
 def sparse_rotations(rots):
@@ -131,10 +131,11 @@ def test_ucc_prefix_and_inverse_return_to_zero_30q(Q):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("t", [13, 14])
+@pytest.mark.parametrize("t", [12, 13, 14])
 def test_large_tiles_30q(Q, t):
-    """2^13- and 2^14-amplitude tiles (512- and 1024-thread workgroups, several
-    tiles per workgroup at 30 qubits): the UCC prefix's nonzero amplitudes
+    """2^12-amplitude tiles (block operands staged in LDS), 2^13- and
+    2^14-amplitude tiles (512- and 1024-thread workgroups, several tiles per
+    workgroup at 30 qubits): the UCC prefix's nonzero amplitudes
     against the closed form, and sampled QFT amplitudes with dense 4- and
     5-qubit blocks."""
     c, rots = qsynth.ucc(N, n_exp=10, seed=3)
