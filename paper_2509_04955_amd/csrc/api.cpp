@@ -379,46 +379,36 @@ qs_status qs_apply_plan(qs_state s, qs_plan p) {
 
 qs_status qs_expect_pauli_sum(qs_state s, const uint64_t *x, const uint64_t *z, const double *coeff, size_t n_terms,
                               double *out, double *out_terms) {
+    QS_ABI_TRY
     QS_CHECK(s && x && z && coeff && out, QS_EINVAL, "null argument");
     QS_CHECK(n_terms >= 1 && n_terms <= (1u << 20), QS_ERANGE, "n_terms %zu outside 1..2^20", n_terms);
     const uint64_t lim = s->n >= 64 ? ~0ull : ((1ull << s->n) - 1);
     for (size_t k = 0; k < n_terms; ++k)
         QS_CHECK((x[k] & ~lim) == 0 && (z[k] & ~lim) == 0, QS_EINVAL, "term %zu acts outside the %d qubits", k, s->n);
-    const size_t ppt = expect_parts_per_term(s->n);
-    uint64_t *d_xz = nullptr;
-    double *d_buf = nullptr;
-    QS_HIP(hipMalloc(&d_xz, 2 * n_terms * sizeof(uint64_t)));
-    hipError_t e = hipMalloc(&d_buf, (n_terms * ppt + n_terms) * sizeof(double));
-    if (e != hipSuccess) {
-        hipFree(d_xz);
-        return hip_fail(e, "hipMalloc(expect)");
-    }
-    std::vector<uint64_t> hxz(2 * n_terms);
-    std::copy(x, x + n_terms, hxz.begin());
-    std::copy(z, z + n_terms, hxz.begin() + n_terms);
-    qs_status st = QS_OK;
     std::vector<double> terms(n_terms);
     double nrm = 0;
-    do {
-        e = hipMemcpyAsync(d_xz, hxz.data(), hxz.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream);
-        if (e != hipSuccess) { st = hip_fail(e, "copy masks"); break; }
-        st = launch_expect(*s, d_xz, d_xz + n_terms, n_terms, d_buf, ppt, d_buf + n_terms * ppt);
-        if (st != QS_OK) break;
-        e = hipMemcpyAsync(terms.data(), d_buf + n_terms * ppt, n_terms * sizeof(double), hipMemcpyDeviceToHost,
-                           s->stream);
-        if (e != hipSuccess) { st = hip_fail(e, "copy terms"); break; }
-        e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) { st = hip_fail(e, "expectation"); break; }
-        // norm of the stored amplitudes (the pending scale cancels in the ratio)
-        st = launch_norm_full(*s, s->d_slots + 2);
-        if (st != QS_OK) break;
-        e = hipMemcpyAsync(&nrm, s->d_slots + 2, sizeof(double), hipMemcpyDeviceToHost, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) { st = hip_fail(e, "norm"); break; }
-    } while (0);
-    hipFree(d_xz);
-    hipFree(d_buf);
-    if (st != QS_OK) return st;
+    // launches of at most kExpTermsPerLaunch terms, each with its own scratch
+    for (size_t k0 = 0; k0 < n_terms; k0 += kExpTermsPerLaunch) {
+        const size_t cnt = std::min(kExpTermsPerLaunch, n_terms - k0);
+        ExpectPlan plan;
+        qs_status st = expect_plan(s->n, s->dtype, x + k0, z + k0, cnt, plan);
+        if (st != QS_OK) return st;
+        void *d_scr = nullptr;
+        QS_HIP(hipMalloc(&d_scr, expect_scratch_bytes(plan)));
+        std::vector<double> res(plan.terms.size());
+        double *d_res = nullptr;
+        st = launch_expect(*s, plan, d_scr, &d_res);
+        hipError_t e = hipSuccess;
+        if (st == QS_OK) {
+            e = hipMemcpyAsync(res.data(), d_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        }
+        hipFree(d_scr);
+        if (st != QS_OK) return st;
+        if (e != hipSuccess) return hip_fail(e, "expectation");
+        if (k0 == 0) nrm = res[0];   // squared norm of the stored amplitudes (a pending scale cancels)
+        std::copy(res.begin() + 1, res.end(), terms.begin() + k0);
+    }
     QS_CHECK(nrm > 0, QS_EINVAL, "state has zero norm");
     double E = 0;
     for (size_t k = 0; k < n_terms; ++k) {
@@ -428,6 +418,7 @@ qs_status qs_expect_pauli_sum(qs_state s, const uint64_t *x, const uint64_t *z, 
     }
     *out = E;
     return QS_OK;
+    QS_ABI_CATCH
 }
 
 qs_status qs_profile_enable(int on) {

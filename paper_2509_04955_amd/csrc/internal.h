@@ -222,10 +222,48 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &pass, int6
 qs_status launch_norm_reduce(qs_state_s &s, uint64_t nparts, double *d_out_slots);
 qs_status launch_norm_full(qs_state_s &s, double *d_out_slots);
 qs_status ensure_partials(qs_state_s &s, size_t count);
-// kernels_expect.hip
-qs_status launch_expect(qs_state_s &s, const uint64_t *d_x, const uint64_t *d_z, size_t n_terms,
-                        double *d_parts, size_t parts_per_term, double *d_terms);
-size_t expect_parts_per_term(int n);
+// kernels_expect.hip: Pauli-sum expectation, one read of the state per group
+// of terms whose high X parts span at most kExpMaxD dimensions
+constexpr int kExpMaxD = 8;            // span dimension of a group (coset = 2^D tiles)
+constexpr int kExpMaxTerms = 8;        // terms per group
+constexpr int kExpCosetBits64 = 14;    // coset of 2^14 complex64 amplitudes = 128 KiB LDS
+constexpr int kExpCosetBits128 = 13;   // 2^13 complex128 amplitudes = 128 KiB LDS
+constexpr int kExpAmps64 = 16;         // amplitudes one thread stages per coset
+constexpr int kExpAmps128 = 8;
+constexpr size_t kExpTermsPerLaunch = 4096;   // user terms per launch (the API splits longer sums)
+constexpr int kExpMaxAmps = 16;        // = max(kExpAmps64, kExpAmps128)
+struct ExpectTerm {
+    uint32_t zh;        // Z mask above the tile bits (the coset's sign)
+    uint32_t xloc;      // X mask in coset coordinates (0: diagonal term)
+    uint32_t zloc;      // Z mask in coset coordinates
+    int32_t imag;       // pairs contribute Im(w) (|x&z| odd) instead of Re(w)
+    double factor;      // +-2 for pairs (phase i^{|x&z|}), 1 for diagonal terms
+    int32_t group;      // the term's group
+    uint32_t x_off;     // xloc in LDS bytes
+    // per staged index m of a thread (pairs: m < NA/2, diagonal: m < NA):
+    uint32_t jm_off[kExpMaxAmps / 2];   // LDS byte offset of ins0(m T, h), h = top bit of xloc
+    double sg[kExpMaxAmps];             // (-1)^parity(ins0(m T, h) & zloc), or of (m T) & zloc
+};
+static_assert(sizeof(ExpectTerm) == 192, "ExpectTerm layout");
+struct ExpectGroup {
+    uint32_t v[kExpMaxD];   // span basis over the high bits (at most 32), reduced echelon
+    int32_t piv[kExpMaxD];  // pivot bit of each basis vector, ascending
+    uint32_t mv[kExpMaxAmps];   // span vector of the tile coordinate of staged amplitude m
+    int32_t term0, nterms;  // the group's terms (contiguous)
+};
+struct ExpectPlan {
+    int n = 0, b = 0, l = 0, D = 0, threads = 0, log_cosets = 0;
+    bool small = false;     // one-wave variant (state smaller than a full coset)
+    uint64_t items = 0;
+    uint32_t grid = 0;
+    std::vector<ExpectTerm> terms;    // term 0 = identity (squared norm), then the caller's terms
+    std::vector<ExpectGroup> groups;
+};
+qs_status expect_plan(int n, qs_dtype dt, const uint64_t *x, const uint64_t *z, size_t n_terms, ExpectPlan &out);
+size_t expect_scratch_bytes(const ExpectPlan &p);
+// d_scratch: expect_scratch_bytes(p) device bytes, 256-byte aligned; *d_out
+// receives the device address of the terms.size() results (term 0 = norm^2)
+qs_status launch_expect(qs_state_s &s, const ExpectPlan &p, void *d_scratch, double **d_out);
 
 // ------------------------------------------------------------ profiling
 bool prof_on();
