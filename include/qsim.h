@@ -181,6 +181,18 @@ qs_status qs_apply_plan(qs_state s, qs_plan p);
 qs_status qs_expect_pauli_sum(qs_state s, const uint64_t *x, const uint64_t *z,
                               const double *coeff, size_t n_terms, double *out,
                               double *out_terms);
+/* The same energy for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * device memory is allocated or freed; the kernels' tables, per-workgroup
+ * partials and results live in a device array the library holds per GPU
+ * until the process ends (about 5 MiB).  At most 2048 terms per call
+ * (QS_ERANGE above).  Calls in one process take turns on a GPU's array (a
+ * lock), and every call leaves the array's contents behind for the next one,
+ * which overwrites what it reads.  Same arguments, results and
+ * synchronisation as qs_expect_pauli_sum. */
+qs_status qs_expect_pauli_sum_noalloc(qs_state s, const uint64_t *x, const uint64_t *z,
+                                      const double *coeff, size_t n_terms, double *out,
+                                      double *out_terms);
 
 /* ------------------------------------------------------------ batches */
 /* A batch of independent states (uneven qubit counts, 1 <= n_i <= 26),

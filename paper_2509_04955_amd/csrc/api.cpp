@@ -103,6 +103,39 @@ qs_status convert_gates(int n, const qs_gate *gates, size_t ng, std::vector<HGat
     return QS_OK;
 }
 
+qs_status check_expect_args(qs_state s, const uint64_t *x, const uint64_t *z, const double *coeff, size_t n_terms,
+                            const double *out) {
+    QS_CHECK(s && x && z && coeff && out, QS_EINVAL, "null argument");
+    QS_CHECK(n_terms >= 1 && n_terms <= (1u << 20), QS_ERANGE, "n_terms %zu outside 1..2^20", n_terms);
+    const uint64_t lim = s->n >= 64 ? ~0ull : ((1ull << s->n) - 1);
+    for (size_t k = 0; k < n_terms; ++k)
+        QS_CHECK((x[k] & ~lim) == 0 && (z[k] & ~lim) == 0, QS_EINVAL, "term %zu acts outside the %d qubits", k, s->n);
+    return QS_OK;
+}
+
+// one expectation launch into d_scr; res (plan.terms.size()) receives the
+// unnormalised terms, res[0] the squared norm.  Synchronises the stream.
+qs_status run_expect(qs_state_s &s, const ExpectPlan &plan, void *d_scr, std::vector<double> &res) {
+    double *d_res = nullptr;
+    qs_status st = launch_expect(s, plan, d_scr, &d_res);
+    if (st != QS_OK) return st;
+    QS_HIP(hipMemcpyAsync(res.data(), d_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, s.stream));
+    QS_HIP(hipStreamSynchronize(s.stream));
+    return QS_OK;
+}
+
+qs_status finish_expect(std::vector<double> &terms, double nrm, const double *coeff, double *out, double *out_terms) {
+    QS_CHECK(nrm > 0, QS_EINVAL, "state has zero norm");
+    double E = 0;
+    for (size_t k = 0; k < terms.size(); ++k) {
+        terms[k] /= nrm;
+        E += coeff[k] * terms[k];
+        if (out_terms) out_terms[k] = terms[k];
+    }
+    *out = E;
+    return QS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -380,44 +413,51 @@ qs_status qs_apply_plan(qs_state s, qs_plan p) {
 qs_status qs_expect_pauli_sum(qs_state s, const uint64_t *x, const uint64_t *z, const double *coeff, size_t n_terms,
                               double *out, double *out_terms) {
     QS_ABI_TRY
-    QS_CHECK(s && x && z && coeff && out, QS_EINVAL, "null argument");
-    QS_CHECK(n_terms >= 1 && n_terms <= (1u << 20), QS_ERANGE, "n_terms %zu outside 1..2^20", n_terms);
-    const uint64_t lim = s->n >= 64 ? ~0ull : ((1ull << s->n) - 1);
-    for (size_t k = 0; k < n_terms; ++k)
-        QS_CHECK((x[k] & ~lim) == 0 && (z[k] & ~lim) == 0, QS_EINVAL, "term %zu acts outside the %d qubits", k, s->n);
+    qs_status st = check_expect_args(s, x, z, coeff, n_terms, out);
+    if (st != QS_OK) return st;
     std::vector<double> terms(n_terms);
     double nrm = 0;
     // launches of at most kExpTermsPerLaunch terms, each with its own scratch
     for (size_t k0 = 0; k0 < n_terms; k0 += kExpTermsPerLaunch) {
         const size_t cnt = std::min(kExpTermsPerLaunch, n_terms - k0);
         ExpectPlan plan;
-        qs_status st = expect_plan(s->n, s->dtype, x + k0, z + k0, cnt, plan);
+        st = expect_plan(s->n, s->dtype, x + k0, z + k0, cnt, plan);
         if (st != QS_OK) return st;
         void *d_scr = nullptr;
         QS_HIP(hipMalloc(&d_scr, expect_scratch_bytes(plan)));
         std::vector<double> res(plan.terms.size());
-        double *d_res = nullptr;
-        st = launch_expect(*s, plan, d_scr, &d_res);
-        hipError_t e = hipSuccess;
-        if (st == QS_OK) {
-            e = hipMemcpyAsync(res.data(), d_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        }
+        st = run_expect(*s, plan, d_scr, res);
         hipFree(d_scr);
         if (st != QS_OK) return st;
-        if (e != hipSuccess) return hip_fail(e, "expectation");
         if (k0 == 0) nrm = res[0];   // squared norm of the stored amplitudes (a pending scale cancels)
         std::copy(res.begin() + 1, res.end(), terms.begin() + k0);
     }
-    QS_CHECK(nrm > 0, QS_EINVAL, "state has zero norm");
-    double E = 0;
-    for (size_t k = 0; k < n_terms; ++k) {
-        terms[k] /= nrm;
-        E += coeff[k] * terms[k];
-        if (out_terms) out_terms[k] = terms[k];
+    return finish_expect(terms, nrm, coeff, out, out_terms);
+    QS_ABI_CATCH
+}
+
+qs_status qs_expect_pauli_sum_noalloc(qs_state s, const uint64_t *x, const uint64_t *z, const double *coeff,
+                                      size_t n_terms, double *out, double *out_terms) {
+    QS_ABI_TRY
+    qs_status st = check_expect_args(s, x, z, coeff, n_terms, out);
+    if (st != QS_OK) return st;
+    QS_CHECK(n_terms <= kNoAllocMaxTerms, QS_ERANGE, "n_terms %zu above the %zu this call holds scratch for",
+             n_terms, kNoAllocMaxTerms);
+    ExpectPlan plan;
+    st = expect_plan(s->n, s->dtype, x, z, n_terms, plan, kNoAllocMaxGrid);
+    if (st != QS_OK) return st;
+    std::vector<double> res(plan.terms.size());
+    {
+        // one user of the device's scratch at a time in this process
+        std::lock_guard<std::mutex> lk(noalloc_lock());
+        void *d_scr = nullptr;
+        st = noalloc_scratch(expect_scratch_bytes(plan), &d_scr);
+        if (st != QS_OK) return st;
+        st = run_expect(*s, plan, d_scr, res);
+        if (st != QS_OK) return st;
     }
-    *out = E;
-    return QS_OK;
+    std::vector<double> terms(res.begin() + 1, res.end());
+    return finish_expect(terms, res[0], coeff, out, out_terms);
     QS_ABI_CATCH
 }
 

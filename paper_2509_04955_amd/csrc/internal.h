@@ -6,6 +6,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <new>
 #include <stdexcept>
@@ -259,11 +260,20 @@ struct ExpectPlan {
     std::vector<ExpectTerm> terms;    // term 0 = identity (squared norm), then the caller's terms
     std::vector<ExpectGroup> groups;
 };
-qs_status expect_plan(int n, qs_dtype dt, const uint64_t *x, const uint64_t *z, size_t n_terms, ExpectPlan &out);
+// max_grid (0 = no limit) caps the workgroups of the launch
+qs_status expect_plan(int n, qs_dtype dt, const uint64_t *x, const uint64_t *z, size_t n_terms, ExpectPlan &out,
+                      uint32_t max_grid = 0);
 size_t expect_scratch_bytes(const ExpectPlan &p);
 // d_scratch: expect_scratch_bytes(p) device bytes, 256-byte aligned; *d_out
 // receives the device address of the terms.size() results (term 0 = norm^2)
 qs_status launch_expect(qs_state_s &s, const ExpectPlan &p, void *d_scratch, double **d_out);
+// the library-held scratch of the no-allocation expectation (kernels_expect.hip):
+// its device address on the current device, taken once per device; need
+// beyond its size gives QS_ERANGE.  noalloc_lock serialises its users.
+constexpr size_t kNoAllocMaxTerms = 2048;
+constexpr uint32_t kNoAllocMaxGrid = 256;
+qs_status noalloc_scratch(size_t need, void **ptr);
+std::mutex &noalloc_lock();
 
 // ------------------------------------------------------------ profiling
 bool prof_on();

@@ -31,6 +31,7 @@
 // squared norm) rides along in the first group at no extra read.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -320,7 +321,8 @@ int device_cus() {
 
 // ------------------------------------------------------------ host plan
 
-qs_status expect_plan(int n, qs_dtype dt, const uint64_t *x, const uint64_t *z, size_t n_terms, ExpectPlan &out) {
+qs_status expect_plan(int n, qs_dtype dt, const uint64_t *x, const uint64_t *z, size_t n_terms, ExpectPlan &out,
+                      uint32_t max_grid) {
     QS_CHECK(n >= 1 && n <= kMaxQubits, QS_EINVAL, "n=%d outside 1..%d", n, kMaxQubits);
     const int bmax = dt == QS_C64 ? kExpCosetBits64 : kExpCosetBits128;
     const int na = dt == QS_C64 ? kExpAmps64 : kExpAmps128;
@@ -443,7 +445,9 @@ qs_status expect_plan(int n, qs_dtype dt, const uint64_t *x, const uint64_t *z, 
     }
     const uint64_t items = (uint64_t)p.groups.size() << p.log_cosets;
     p.items = items;
-    p.grid = (uint32_t)std::min<uint64_t>((uint64_t)device_cus(), items);
+    uint64_t grid = (uint64_t)device_cus();
+    if (max_grid) grid = std::min<uint64_t>(grid, max_grid);
+    p.grid = (uint32_t)std::min<uint64_t>(grid, items);
     out = std::move(p);
     return QS_OK;
 }
@@ -498,6 +502,53 @@ qs_status launch_expect(qs_state_s &s, const ExpectPlan &p, void *d_scratch, dou
     QS_HIP(hipGetLastError());
     *d_out = d_res;
     return QS_OK;
+}
+
+// ------------------------------------------------- library-held scratch
+// Device memory for qs_expect_pauli_sum_noalloc: term and group tables,
+// per-workgroup partials and results of one launch of at most
+// kNoAllocMaxTerms caller terms.  Every device the library runs on holds one
+// copy until the process ends.  Nothing in it needs clearing between calls:
+// the tables are copied in whole, each partial the reduction reads is written
+// by the same launch, and the results are written by the reduction.
+namespace {
+
+constexpr size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t kNoAllocScratchBytes =
+    up256((kNoAllocMaxTerms + 1) * sizeof(ExpectTerm)) + up256((kNoAllocMaxTerms + 1) * sizeof(ExpectGroup)) +
+    up256((size_t)kNoAllocMaxGrid * (kNoAllocMaxTerms + 1) * sizeof(double)) +
+    up256((kNoAllocMaxTerms + 1) * sizeof(double));
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+qs_status noalloc_scratch(size_t need, void **ptr) {
+    QS_CHECK(need <= kNoAllocScratchBytes, QS_ERANGE, "scratch of %zu bytes exceeds the %zu held", need,
+             kNoAllocScratchBytes);
+    int dev = 0;
+    QS_HIP(hipGetDevice(&dev));
+    QS_CHECK(dev >= 0 && dev < kMaxDevices, QS_EDEVICE, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        // the array's device address on the current device (its host-side name
+        // is not a device address)
+        void *p = nullptr;
+        QS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        QS_CHECK(p != nullptr, QS_EDEVICE, "scratch has no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return QS_OK;
+}
+
+std::mutex &noalloc_lock() {
+    static std::mutex mu;
+    return mu;
 }
 
 }  // namespace qs

@@ -80,6 +80,7 @@ _SIGS = {
     "qs_plan_pass": ([_vp, _u64, _vp, _vp, _vp, _vp], _i32),
     "qs_apply_plan": ([_vp, _vp], _i32),
     "qs_expect_pauli_sum": ([_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp], _i32),
+    "qs_expect_pauli_sum_noalloc": ([_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp], _i32),
     "qs_batch_create": ([_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "qs_batch_destroy": ([_vp], _i32),
     "qs_batch_run": ([_vp, _vp], _i32),
@@ -268,6 +269,16 @@ def qs_expect_pauli_sum(h, x, z, coeff, with_terms: bool = False):
     out = ctypes.c_double()
     terms = np.zeros(len(c), dtype=np.float64) if with_terms else None
     _check(lib().qs_expect_pauli_sum(h, _p(x), _p(z), _p(c), len(c), ctypes.byref(out), _p(terms)))
+    return (out.value, terms) if with_terms else out.value
+
+
+def qs_expect_pauli_sum_noalloc(h, x, z, coeff, with_terms: bool = False):
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    c = np.ascontiguousarray(coeff, dtype=np.float64)
+    out = ctypes.c_double()
+    terms = np.zeros(len(c), dtype=np.float64) if with_terms else None
+    _check(lib().qs_expect_pauli_sum_noalloc(h, _p(x), _p(z), _p(c), len(c), ctypes.byref(out), _p(terms)))
     return (out.value, terms) if with_terms else out.value
 
 
