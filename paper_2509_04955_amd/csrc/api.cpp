@@ -172,8 +172,10 @@ qs_status qs_state_create(int n, qs_dtype dtype, void *dev_ptr, void *stream, qs
     s->dtype = dtype;
     s->stream = (hipStream_t)stream;
     hipGetDevice(&s->device);
-    hipError_t e = hipMalloc(&s->d_slots, 4 * sizeof(double));
+    hipError_t e = hipMalloc(&s->d_slots, kNumSlots * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(s->d_slots, 0, kNumSlots * sizeof(double));   // ticket counter at 0
     if (e != hipSuccess) {
+        if (s->d_slots) hipFree(s->d_slots);
         delete s;
         return hip_fail(e, "hipMalloc(slots)");
     }

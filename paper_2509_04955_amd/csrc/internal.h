@@ -69,6 +69,7 @@ enum : int32_t {
     BK_PAULI = 4,   // Pauli rotation: y[k] = c psi[k] + d sigma(k^x) psi[k^x]
     BK_PAULIG = 5,  // k consecutive Pauli rotations with independent X parts, one lane per coset
     BK_SKIP = 6,    // folded into the preceding group (no work, no barrier)
+    BK_BDMFMA = 7,  // complex64 permuted block-diagonal, classes of 4 or 8, on MFMA (staged passes)
 };
 
 struct BlockDev {
@@ -98,6 +99,8 @@ struct PassArgs {
 struct Prof;
 }  // namespace qs
 
+constexpr int kNumSlots = 8;
+constexpr int kSlotTickets = 4;
 struct qs_state_s {
     int n = 0;
     qs_dtype dtype = QS_C64;
@@ -105,8 +108,11 @@ struct qs_state_s {
     bool owned = false;
     hipStream_t stream = nullptr;
     int device = 0;
-    // FP64 norm chain: slot[0] = norm of last pass, slot[1] = scale to apply next.
+    // FP64 norm chain: slot[0] = norm of last pass, slot[1] = scale to apply next,
+    // slots 2/3 scratch norm; slot kSlotTickets holds the tile-pass ticket
+    // counter (64-bit, zero at creation) whose value the host mirrors in tickets.
     double *d_slots = nullptr;
+    uint64_t tickets = 0;
     double *d_partials = nullptr;
     size_t partials_cap = 0;
     bool scale_pending = false;

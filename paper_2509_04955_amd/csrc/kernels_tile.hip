@@ -103,7 +103,8 @@ constexpr size_t kRedBytes = 128;   // NT / 64 doubles for up to 1024 threads
 template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
 __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_tile_pass(
     typename AmpOf<R>::A *__restrict__ psi, uint64_t ntiles, PassArgs pa, const BlockDev *__restrict__ blocks,
-    const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials) {
+    const R *__restrict__ pool, const double *__restrict__ scale_in, double *__restrict__ partials,
+    unsigned long long *__restrict__ tickets, unsigned long long ticket0) {
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
@@ -159,12 +160,21 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
                 if (j0 + i < nj) lds_put(j0 + i, pre[i]);
         }
     };
-    uint64_t tileid = blockIdx.x;
-    if (tileid >= ntiles) {   // whole workgroup
-        if (pa.want_norm && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
-        return;
+    // Tiles are handed out in ascending order by a ticket counter (the state's,
+    // advanced by ntiles + grid per pass: every workgroup draws until it gets
+    // a ticket past the last tile), so a workgroup that runs faster than its
+    // neighbour on the same CU takes more tiles.  Thread 0 draws the ticket
+    // after next into an LDS slot; the loop-top barrier publishes it.
+    __shared__ uint64_t next_slot[2];
+    if (threadIdx.x == 0) {
+        next_slot[0] = atomicAdd(tickets, 1ull) - ticket0;
+        // exactly one ticket past the last tile per workgroup
+        next_slot[1] = next_slot[0] < ntiles ? atomicAdd(tickets, 1ull) - ticket0 : ntiles;
     }
-    double wg_norm = 0.0;   // thread 0: this workgroup's tiles, in tile order
+    __syncthreads();
+    uint64_t tileid = next_slot[0];
+    uint64_t nxt = next_slot[1];
+    if (tileid >= ntiles) return;   // whole workgroup
     // block operands of the pass -> LDS behind the tile (once per workgroup;
     // pool entries are 16-byte aligned and cl_len a multiple of 16 bytes)
     if constexpr (CL) {
@@ -197,9 +207,12 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     // registers before the blocks, the remaining vectors after them), so the
     // waits for them at the bottom of the loop leave the stores in flight.
     // On the last tile the loads re-read the current tile (in bounds, unused).
+    int slot = 0;
     for (;;) {
         __syncthreads();
-        const uint64_t nxt = tileid + gridDim.x;
+        if (slot) nxt = next_slot[slot & 1];
+        // the ticket after next, read by every thread behind the next loop-top barrier
+        if (threadIdx.x == 0 && nxt < ntiles) next_slot[(slot + 1) & 1] = atomicAdd(tickets, 1ull) - ticket0;
         const bool more = nxt < ntiles;   // uniform over the workgroup
         const uint64_t nbase = more ? tile_base(nxt, pa) : base;
         if (active) {
@@ -244,7 +257,7 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
             double s = 0;
 #pragma unroll
             for (int w = 0; w < NT / 64; ++w) s += red[w];
-            wg_norm += s;
+            partials[tileid] = s;   // one partial per tile: the reduction order does not depend on the schedule
         }
         if (!more) break;
         if (active) {
@@ -260,8 +273,8 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
         }
         tileid = nxt;
         base = nbase;
+        ++slot;
     }
-    if (pa.want_norm && threadIdx.x == 0) partials[blockIdx.x] = wg_norm;
 }
 
 // one workgroup: fixed-order FP64 sum of the partials; slot[0] = N, slot[1] = 1/sqrt(N)
@@ -314,7 +327,7 @@ bool big_tiles_enabled() {
 
 template <typename R>
 using TileKernel = void (*)(typename AmpOf<R>::A *, uint64_t, PassArgs, const BlockDev *, const R *, const double *,
-                            double *);
+                            double *, unsigned long long *, unsigned long long);
 
 // Kernel variant for a pass: register footprint (wide), LDS-staged operands
 // (cl) and, for the narrow variant, the compile-time vector count.
@@ -560,6 +573,17 @@ bool bdiag_supported(int k, int s, qs_dtype dt) {
     return gap > 0 && k >= 3 && k <= 4 && s >= 0 && s <= k - gap;
 }
 
+// QS_TILE_BDMFMA=0: permuted block-diagonal blocks stay on the vector ALU in
+// staged passes
+bool bdmfma_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("QS_TILE_BDMFMA");
+        v = e ? atoi(e) != 0 : 1;
+    }
+    return v == 1;
+}
+
 bool staged_enabled() {
     static int v = -1;
     if (v < 0) {
@@ -721,7 +745,39 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
     const int D = 1 << d.k;
     std::vector<int> dest;
     const int kind = block_kind(blk, t, dt, &dest, lds);
-    if (kind == BK_BDIAG) {
+    if (kind == BK_BDMFMA) {
+        // packs of 8 class members (one class of 8 or two of 4), see
+        // bdiag_mfma_block: A of the pack's 16x16 real form as [lane][step],
+        // column offsets (members 0,2,4,6 then 1,3,5,7), row offsets
+        int sub = 0;
+        std::vector<int> src, dst;
+        bdiag_split(blk.U, d.k, sub, src, dst);
+        d.kind = BK_BDMFMA;
+        d.sub = sub;
+        d.mat_off = (int32_t)pool.size();
+        auto off = [&](int c) {
+            uint32_t o = 0;
+            for (int j = 0; j < d.k; ++j)
+                if ((c >> j) & 1) o |= 1u << d.pos[j];
+            return sw(o) * 2 * (uint32_t)sizeof(R);
+        };
+        const int DS = 1 << sub;
+        for (int p0 = 0; p0 < D; p0 += 8) {
+            for (int lane = 0; lane < 64; ++lane)
+                for (int st = 0; st < 4; ++st) {
+                    const int i = lane % 16, kk = 4 * st + lane / 16;
+                    const int r = i / 2, rp = i % 2, c = kk / 2, cp = kk % 2;
+                    // zero between classes (entries there are rounding residue)
+                    const bool same = (p0 + r) / DS == (p0 + c) / DS;
+                    const cd u = same ? blk.U[(size_t)dst[p0 + r] * D + src[p0 + c]] : cd(0.0, 0.0);
+                    const double v = rp == 0 ? (cp == 0 ? u.real() : -u.imag()) : (cp == 0 ? u.imag() : u.real());
+                    pool.push_back((R)v);
+                }
+            for (int h = 0; h < 2; ++h)
+                for (int st = 0; st < 4; ++st) pool.push_back(pool_entry<R>(off(src[p0 + 2 * st + h])));
+            for (int r = 0; r < 8; ++r) pool.push_back(pool_entry<R>(off(dst[p0 + r])));
+        }
+    } else if (kind == BK_BDIAG) {
         // record: 2^k swizzled source offsets (class by class), 2^k swizzled
         // destination offsets, then the classes' 2^s x 2^s matrices
         int sub = 0;
@@ -791,7 +847,7 @@ double block_flops_per_amp(const BlockDev &d) {
     if (d.kind == BK_PAULIG) return 16.0 * d.k;
     if (d.kind == BK_SKIP) return 0.0;
     if (d.kind == BK_MONO) return 6.0;
-    if (d.kind == BK_BDIAG) return 8.0 * (1 << d.sub);
+    if (d.kind == BK_BDIAG || d.kind == BK_BDMFMA) return 8.0 * (1 << d.sub);
     return 8.0 * (1 << d.k);
 }
 
@@ -803,6 +859,7 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
         size_t e = kind == BK_PAULI   ? 52   // bound: a group record (pivots, 16 offsets, 4 x 8)
+                   : kind == BK_BDMFMA  ? (size_t)(D / 8) * kBdPackFloats
                    : kind == BK_MONO    ? 4 * (size_t)D
                    : kind == BK_MFMA  ? (k == 4 || (k == 5 && !big_staged(ps.t, dt)) ? (size_t)3 * D * D
                                                                                       : (size_t)4 * D * D)
@@ -847,8 +904,13 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     int sub = 0;
     std::vector<int> src, dst;
     if (structured_enabled() && bdiag_gap() > 0 && k >= 3 && bdiag_split(b.U, k, sub, src, dst) &&
-        bdiag_supported(k, sub, dt))
+        bdiag_supported(k, sub, dt)) {
+        // complex64 classes of 4 or 8 in staged passes: 16x16 real products on MFMA
+        if (lds && dt == QS_C64 && mfma_enabled() && bdmfma_enabled() && t - k >= 4 && sub >= 2 &&
+            (k == 4 || (k == 3 && sub == 2)))
+            return BK_BDMFMA;
         return BK_BDIAG;
+    }
     // complex64: MFMA for k = 4, 5 (k = 3 too when staged); complex128: FP64
     // MFMA only in staged passes (the unstaged FP64 path is the vector ALU)
     if (t - k >= 4 && mfma_enabled()) {
@@ -874,7 +936,7 @@ bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
         const int k = (int)blocks[b].qubits.size();
         const int kind = block_kind(blocks[b], ps.t, dt, nullptr, true);
-        per_lane |= kind == BK_MFMA || (kind == BK_MONO && k >= 4);
+        per_lane |= kind == BK_MFMA || kind == BK_BDMFMA || (kind == BK_MONO && k >= 4);
         dense_wide |= kind == BK_DENSE && k > 3;
     }
     return per_lane && !dense_wide && pass_operand_bytes(blocks, ps, dt) <= budget;
@@ -1012,23 +1074,28 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     const uint64_t resident = resident_groups(fn, threads, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
     if (want_norm) {
-        qs_status st = ensure_partials(s, grid.x);
+        qs_status st = ensure_partials(s, ntiles);
         if (st != QS_OK) return st;
     }
-    if (nparts) *nparts = grid.x;
+    if (nparts) *nparts = ntiles;   // one norm partial per tile
     const double S = std::ldexp((double)amp, s.n);
     double flops = 0;
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b)
         flops += block_flops_per_amp(p.h_blocks[di][b]) * std::ldexp(1.0, s.n);
     prof_begin(s.stream, QS_PROF_TILE, 2 * S, flops);
+    unsigned long long *tickets = reinterpret_cast<unsigned long long *>(s.d_slots + kSlotTickets);
     if (s.dtype == QS_C64)
         hipLaunchKernelGGL(k32, grid, dim3(threads), lds, s.stream, (float2 *)s.amp, ntiles,
-                           pa, p.d_blocks[di], (const float *)p.d_pool[di], s.d_slots + 1, s.d_partials);
+                           pa, p.d_blocks[di], (const float *)p.d_pool[di], s.d_slots + 1, s.d_partials, tickets,
+                           (unsigned long long)s.tickets);
     else
         hipLaunchKernelGGL(k64, grid, dim3(threads), lds, s.stream, (double2 *)s.amp,
-                           ntiles, pa, p.d_blocks[di], (const double *)p.d_pool[di], s.d_slots + 1, s.d_partials);
+                           ntiles, pa, p.d_blocks[di], (const double *)p.d_pool[di], s.d_slots + 1, s.d_partials,
+                           tickets, (unsigned long long)s.tickets);
     prof_end(s.stream);
     QS_HIP(hipGetLastError());
+    // every tile's ticket plus one past the end per workgroup
+    s.tickets += ntiles + grid.x;
     return QS_OK;
 }
 

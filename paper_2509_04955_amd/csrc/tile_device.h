@@ -775,6 +775,87 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
     }
 }
 
+// ---- permuted block-diagonal block on MFMA (complex64, staged) -----------
+// The classes of a block (2^S rows and columns each, S = 2 or 3) are taken
+// eight members at a time ("packs": one class of 8 or two of 4); a pack acts
+// on its 8 column amplitudes as an 8x8 complex matrix M (zero between
+// classes) and writes its 8 row amplitudes.  Its real form is one 16x16
+// product per 16 groups: rows and K both ordered (member, re/im), so with
+// v_mfma_f32_16x16x4f32 lane l supplies A[l % 16][4 s + l / 16] and, at step s,
+// part (l / 16) % 2 of member 2 s + l / 32 of group l % 16; output q of lane l
+// is row 4 (l / 16) + q, i.e. both parts of members 2 (l / 16) and
+// 2 (l / 16) + 1.  Staged record per pack: A as [lane][s] (256 floats), the
+// column offsets ordered members 0,2,4,6 then 1,3,5,7, the row offsets in
+// member order (swizzled LDS byte offsets).  A wave owns whole 16-group
+// chunks and reads every pack of a chunk before writing any (a pack's rows
+// may be another pack's columns), so the block needs no barrier.
+constexpr int kBdPackFloats = 256 + 8 + 8;
+
+template <int K, int NT = TT>
+__device__ __forceinline__ void bdiag_mfma_block(float2 *tile, int T, const BlockDev *bd, const float *Es) {
+    constexpr int NPK = (1 << K) / 8;
+    constexpr int CPI = 2;   // chunks in flight per wave
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, jc = lane & 15;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    // per pack: this lane's A values, its 4 column offsets (with the part's
+    // 4-byte shift), its 2 row offsets
+    floatx4 a[NPK];
+    uint32_t io[NPK][4], oo[NPK][2];
+#pragma unroll
+    for (int p = 0; p < NPK; ++p) {
+        const float *E = Es + p * kBdPackFloats;
+        a[p] = reinterpret_cast<const floatx4 *>(E)[lane];
+        const uint32_t *ib = reinterpret_cast<const uint32_t *>(E + 256) + 4 * (g >> 1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) io[p][s] = ib[s] | (uint32_t)((g & 1) << 2);
+        const uint32_t *ob = reinterpret_cast<const uint32_t *>(E + 264) + 2 * g;
+        oo[p][0] = ob[0];
+        oo[p][1] = ob[1];
+    }
+    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
+    const uint32_t nchunks = (1u << (T - K)) / 16;
+    for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += (NT / 64) * CPI) {
+        uint32_t sb[CPI];
+        float x[CPI][NPK][4];
+#pragma unroll
+        for (int h = 0; h < CPI; ++h) {
+            const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
+            uint32_t b = ch * 16 + jc;
+#pragma unroll
+            for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
+            sb[h] = sw(b) * (uint32_t)sizeof(float2);
+#pragma unroll
+            for (int p = 0; p < NPK; ++p)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) x[h][p][s] = *reinterpret_cast<const float *>(tb + (sb[h] ^ io[p][s]));
+        }
+        floatx4 acc[CPI][NPK];
+#pragma unroll
+        for (int h = 0; h < CPI; ++h)
+#pragma unroll
+            for (int p = 0; p < NPK; ++p) {
+                acc[h][p] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[h][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p][s], x[h][p][s], acc[h][p], 0, 0, 0);
+            }
+#pragma unroll
+        for (int h = 0; h < CPI; ++h) {
+            if (ch0 + h < nchunks) {
+#pragma unroll
+                for (int p = 0; p < NPK; ++p) {
+                    *reinterpret_cast<float2 *>(tb + (sb[h] ^ oo[p][0])) = make_float2(acc[h][p][0], acc[h][p][1]);
+                    *reinterpret_cast<float2 *>(tb + (sb[h] ^ oo[p][1])) = make_float2(acc[h][p][2], acc[h][p][3]);
+                }
+            }
+        }
+    }
+}
+
 // ---- the pass kernel ------------------------------------------------------
 // WIDE = false keeps register use low (dense VALU blocks up to k = 3, complex64
 // dense k = 4, 5 through MFMA, monomial blocks of any width); WIDE = true adds
@@ -803,6 +884,14 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
         if (kind == BK_PAULIG) {
             if (k == 2) pauli_group<R, 2, NT>(tile, T, U, gbase);
             else pauli_group<R, 3, NT>(tile, T, U, gbase);
+            return;
+        }
+    }
+    if constexpr (CL && F32) {
+        if (kind == BK_BDMFMA) {
+            const float *Es = cst + (bd->mat_off - cl_off);
+            if (k == 4) bdiag_mfma_block<4, NT>(tile, T, bd, Es);
+            else bdiag_mfma_block<3, NT>(tile, T, bd, Es);
             return;
         }
     }

@@ -390,3 +390,66 @@ def test_copy_kernel(Q):
     Q.qs_copy(b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def _class_log_width(U, tol=1e-14):
+    """log2 of the widest connected component of U's nonzero pattern (rows
+    against columns): the class width of a permuted block-diagonal block."""
+    D = U.shape[0]
+    parent = list(range(2 * D))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for r in range(D):
+        for c in range(D):
+            if abs(U[r, c]) > tol:
+                parent[find(r)] = find(D + c)
+    sizes = {}
+    for r in range(D):
+        sizes[find(r)] = sizes.get(find(r), 0) + 1
+    w = max(sizes.values())
+    return int(np.ceil(np.log2(w))) if w > 1 else 0
+
+
+@pytest.mark.parametrize("t", [11, 12, 13])
+@pytest.mark.parametrize("family", ["ucc", "perm"])
+def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
+    """Staged complex64 passes put 3- and 4-qubit blocks with classes of 4 or
+    8 amplitudes on the matrix cores (16x16 real products of eight class
+    members at a time); the plan must contain such blocks and the state must
+    match the oracle."""
+    from paper_2509_04955_amd import costmodel
+
+    n = 16
+    if family == "ucc":
+        c, _ = qsynth.ucc(n, n_exp=40, seed=80 + t)
+    else:
+        c = qsynth.random_circuit(n, 400, seed=90 + t, kinds=["cx", "cx", "cz", "rz", "t", "s", "x", "h"])
+    gl = Q.GateList(c)
+    plan = Q.qs_contract(n, gl, Q.opts(k_max=4, tile_qubits=t, low_qubits=4))
+    try:
+        f = costmodel.pass_features(plan)
+        info = Q.qs_plan_info_get(plan)
+        hits = 0
+        for p in range(info.n_passes):
+            if f[p, 14] < 0.5:
+                continue
+            _, _, b0, nb = Q.qs_plan_pass(plan, p)
+            for b in range(b0, b0 + nb):
+                qs, U, _ = Q.qs_plan_block(plan, b)
+                k = len(qs)
+                s = _class_log_width(U)
+                if (k == 4 and s in (2, 3)) or (k == 3 and s == 2):
+                    hits += 1
+        assert hits > 0, "no class blocks of width 4 or 8 in staged passes"
+    finally:
+        Q.qs_plan_destroy(plan)
+    psi0 = qsynth.random_state(n, seed=13)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, 0, psi0, k_max=4, tile_qubits=t, low_qubits=4)
+    assert oracle.max_abs(ref, got) <= TOL64
+    assert 1 - oracle.fidelity(ref, got) <= 1e-6
