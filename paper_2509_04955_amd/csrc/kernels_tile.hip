@@ -905,9 +905,10 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     std::vector<int> src, dst;
     if (structured_enabled() && bdiag_gap() > 0 && k >= 3 && bdiag_split(b.U, k, sub, src, dst) &&
         bdiag_supported(k, sub, dt)) {
-        // complex64 classes of 4 or 8 in staged passes: 16x16 real products on MFMA
-        if (lds && dt == QS_C64 && mfma_enabled() && bdmfma_enabled() && t - k >= 4 && sub >= 2 &&
-            (k == 4 || (k == 3 && sub == 2)))
+        // complex64 4-qubit blocks with classes of 8 in staged passes: 16x16 real
+        // products on MFMA (32 multiply-adds per amplitude on the vector ALU;
+        // classes of 4 measured slower there, the MFMA doing twice their work)
+        if (lds && dt == QS_C64 && mfma_enabled() && bdmfma_enabled() && t - k >= 4 && k == 4 && sub == 3)
             return BK_BDMFMA;
         return BK_BDIAG;
     }

@@ -776,8 +776,8 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
 }
 
 // ---- permuted block-diagonal block on MFMA (complex64, staged) -----------
-// The classes of a block (2^S rows and columns each, S = 2 or 3) are taken
-// eight members at a time ("packs": one class of 8 or two of 4); a pack acts
+// The classes of a block (2^S rows and columns each; the host uses S = 3) are
+// taken eight members at a time ("packs": one class of 8, or two of 4); a pack acts
 // on its 8 column amplitudes as an 8x8 complex matrix M (zero between
 // classes) and writes its 8 row amplitudes.  Its real form is one 16x16
 // product per 16 groups: rows and K both ordered (member, re/im), so with
@@ -890,8 +890,7 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     if constexpr (CL && F32) {
         if (kind == BK_BDMFMA) {
             const float *Es = cst + (bd->mat_off - cl_off);
-            if (k == 4) bdiag_mfma_block<4, NT>(tile, T, bd, Es);
-            else bdiag_mfma_block<3, NT>(tile, T, bd, Es);
+            bdiag_mfma_block<4, NT>(tile, T, bd, Es);
             return;
         }
     }
