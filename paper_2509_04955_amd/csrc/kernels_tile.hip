@@ -821,6 +821,7 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
         d.mat_off = (int32_t)pool.size();
         if (lds && d.k >= 4 && !(d.k == 5 && big_staged(t, dt))) swizzle_mfma3m<R>(blk.U, d.k, pool);
         else swizzle_mfma<R>(blk.U, d.k, lds, pool);
+        if (!lds && (dt == QS_C128 || d.k == 6)) wide = true;
     } else {
         d.kind = BK_DENSE;
         d.mat_off = (int32_t)pool.size();
@@ -912,11 +913,14 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
             return BK_BDMFMA;
         return BK_BDIAG;
     }
-    // complex64: MFMA for k = 4, 5 (k = 3 too when staged); complex128: FP64
-    // MFMA only in staged passes (the unstaged FP64 path is the vector ALU)
+    // complex64: MFMA for k = 4, 5 (k = 3 too when staged) and, unstaged, 6;
+    // complex128: FP64 MFMA for k = 3..5 when staged and k = 4, 5 unstaged.
+    // Unstaged complex128 and k = 6 blocks run in the wide kernel variant.
+    // A staged pass never holds a 6-qubit block (its operands exceed the LDS
+    // left beside the tile): asked for a staged pass, k = 6 reports dense.
     if (t - k >= 4 && mfma_enabled()) {
-        if (dt == QS_C64 && (k == 4 || k == 5 || (lds && k == 3))) return BK_MFMA;
-        if (dt == QS_C128 && lds && k >= 3 && k <= 5) return BK_MFMA;
+        if (dt == QS_C64 && (k == 4 || k == 5 || (lds && k == 3) || (!lds && k == 6))) return BK_MFMA;
+        if (dt == QS_C128 && ((lds && k >= 3 && k <= 5) || (!lds && (k == 4 || k == 5)))) return BK_MFMA;
     }
     return BK_DENSE;
 }

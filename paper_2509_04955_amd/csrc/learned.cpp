@@ -45,7 +45,7 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
             ++nbd;
             flops += 8.0 * (1 << bdiag_log_width(blk));
         } else if (kind == BK_MFMA) {
-            (k == 3 ? n3m : k == 4 ? n4 : n5)++;
+            (k == 3 ? n3m : k == 4 ? n4 : n5)++;   // n5: 5- and 6-qubit MFMA blocks
             flops += 8.0 * (1 << k);
         } else {
             if (k <= 3) ++nd[k];

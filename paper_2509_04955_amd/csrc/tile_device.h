@@ -480,29 +480,41 @@ __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, c
     }
 }
 
-// ---- MFMA block (complex64, K = 4 or 5) ---------------------------------
+// ---- MFMA block, operands from the pool (K = 4, 5; complex64 also 6) --------
 // Y = A X with A = [[Ur, -Ui], [Ui, Ur]] (2D x 2D, D = 2^K) and X the 2D x N
 // real view of the tile (rows: Re then Im of the block's 2^K amplitudes;
-// columns: the other tile positions).  v_mfma_f32_16x16x4f32: lane l supplies
-// A[l%16][kk] and B[kk][l%16] with kk = 4s + l/16 for step s; K-order is
-// chosen so step s reads row 4(s/2) + l/16 of X, real part for even s and
-// imaginary for odd s, and output register q of lane l is row 4(l/16) + q.
-// Each wave owns one 16-row M-tile (its slice of A stays in 2^(K-1) VGPRs):
-// K = 5 has 4 M-tiles, one per wave; K = 4 has 2, and the waves sharing one
-// split the columns.  Columns go in rounds of 4 chunks of 16 per wave: all
-// waves read their inputs, a barrier, then all write (in place).
-template <int K, int NT = TT>
-__device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *bd, const float *__restrict__ Asw) {
+// columns: the other tile positions).  16x16x4 MFMA (FP32 or FP64): lane l
+// supplies A[l%16][kk] and B[kk][l%16] with kk = 4s + l/16 for step s;
+// K-order is chosen so step s reads row 4(s/2) + l/16 of X, real part for
+// even s and imaginary for odd s, and output register q of lane l is row
+// Mfma::row(l/16, q) of the M-tile.  Each wave owns MPW 16-row M-tiles (their
+// slice of A stays in MPW * 2^(K-1) registers): with fewer M-tiles than waves
+// the waves sharing one split the columns, with more (K = 6: 8 M-tiles over
+// 4 waves) each wave runs two.  Columns go in rounds of 4 chunks of 16 per
+// wave: all waves read their inputs, a barrier, then all write (in place).
+// The A loads are vector loads from the pool: a pass with such blocks waits
+// for its tile prefetch at the first of them, which is why complex128 blocks
+// and K = 6 take this path only in the wide variant (whose prefetch is short
+// and whose other blocks are on the vector ALU anyway).
+template <int K, typename R, int NT = TT>
+__device__ __forceinline__ void mfma_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
+                                           const R *__restrict__ Asw) {
+    using A = typename AmpOf<R>::A;
+    using V4 = typename Mfma<R>::V4;
     constexpr int D = 1 << K;
     constexpr int MT = 2 * D / 16;
     constexpr int S = 2 * D / 4;
     constexpr int NB = D / 4;
-    constexpr int CPW = (NT / 64) / MT;   // waves per M-tile
-    constexpr int CR = 4;         // chunks per wave per round
+    constexpr int NW = NT / 64;
+    static_assert(MT % NW == 0 || NW % MT == 0, "M-tiles and waves must divide");
+    constexpr int MPW = MT > NW ? MT / NW : 1;   // M-tiles per wave
+    constexpr int GW = MT / MPW;                 // wave groups (one per M-tile set)
+    constexpr int CPW = NW / GW;                 // waves sharing an M-tile set
+    constexpr int CR = 4;                        // chunks per wave per round
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gq = lane >> 4, jc = lane & 15;
-    const int mt = wave % MT, wsub = wave / MT;
+    const int mt0 = (wave % GW) * MPW, wsub = wave / GW;
     int pos[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
@@ -513,31 +525,38 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
             if ((r >> j) & 1) o |= 1u << pos[j];
         return o;
     };
-    float a[S];
+    R a[MPW][S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) a[s] = Asw[(mt * S + s) * 64 + lane];
+    for (int i = 0; i < MPW; ++i)
+#pragma unroll
+        for (int s = 0; s < S; ++s) a[i][s] = Asw[((mt0 + i) * S + s) * 64 + lane];
     uint32_t offB[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq));
-    const int half = MT / 2;
-    const int part = mt >= half ? 1 : 0;  // 0: real rows, 1: imaginary rows
-    uint32_t offC[4];
+    // float index of output (i, q) relative to 2 * (chunk column base):
+    // 2 * sw(row offset) | part (0: real rows, 1: imaginary rows)
+    uint32_t oc[MPW][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) offC[q] = sw(deposit(16 * (mt % half) + 4 * gq + q));
-    float *tf = reinterpret_cast<float *>(tile);
+    for (int i = 0; i < MPW; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 16 * (mt0 + i) + Mfma<R>::row(gq, q);
+            oc[i][q] = (2u * sw(deposit(row % D))) | (uint32_t)(row / D);
+        }
+    R *tf = reinterpret_cast<R *>(tile);
     const uint32_t nchunks = (1u << (T - K)) / 16;
     for (uint32_t r0 = 0; r0 < nchunks; r0 += CR * CPW) {
-        floatx4 acc[CR];
+        V4 acc[CR][MPW];
         uint32_t cbs[CR];
         // chunks in pairs: two independent accumulator chains per step
 #pragma unroll
         for (int i0 = 0; i0 < CR; i0 += 2) {
-            float2 bv[2][NB];
+            A bv[2][NB];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int i = i0 + h;
-                acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
-                cbs[i] = 0;
+#pragma unroll
+                for (int m = 0; m < MPW; ++m) acc[i][m] = V4{0, 0, 0, 0};
                 const uint32_t ch = r0 + wsub + CPW * i;
                 uint32_t cb = (ch < nchunks ? ch : 0) * 16 + jc;
 #pragma unroll
@@ -550,9 +569,11 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
 #pragma unroll
             for (int s = 0; s < S; ++s)
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
-                    acc[i0 + h] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        a[s], (s & 1) ? bv[h][s >> 1].y : bv[h][s >> 1].x, acc[i0 + h], 0, 0, 0);
+                for (int m = 0; m < MPW; ++m)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        acc[i0 + h][m] = Mfma<R>::op(a[m][s], (s & 1) ? bv[h][s >> 1].y : bv[h][s >> 1].x,
+                                                     acc[i0 + h][m]);
         }
         __syncthreads();
 #pragma unroll
@@ -560,7 +581,9 @@ __device__ __forceinline__ void mfma_block(float2 *tile, int T, const BlockDev *
             const uint32_t ch = r0 + wsub + CPW * i;
             if (ch < nchunks) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) tf[2 * (cbs[i] ^ offC[q]) + part] = acc[i][q];
+                for (int m = 0; m < MPW; ++m)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tf[(2u * cbs[i]) ^ oc[m][q]] = acc[i][m][q];
             }
         }
         __syncthreads();
@@ -902,9 +925,15 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
             else if constexpr (NT > TT) mfma_block_lds<5, R, NT>(tile, T, bd, As);
             else mfma3m_block_lds<5, R, NT>(tile, T, bd, As);
             return;
-        } else if constexpr (F32) {
-            if (k == 4) mfma_block<4, NT>(tile, T, bd, U);
-            else mfma_block<5, NT>(tile, T, bd, U);
+        } else if constexpr (F32 && !WIDE) {
+            if (k == 4) mfma_block<4, R, NT>(tile, T, bd, U);
+            else mfma_block<5, R, NT>(tile, T, bd, U);
+            return;
+        } else if constexpr (WIDE) {
+            // the wide variant: complex128 K = 4, 5 and complex64 K = 4..6
+            if (k == 4) mfma_block<4, R, NT>(tile, T, bd, U);
+            else if (k == 5) mfma_block<5, R, NT>(tile, T, bd, U);
+            else if constexpr (F32) mfma_block<6, R, NT>(tile, T, bd, U);
             return;
         }
     }

@@ -193,6 +193,44 @@ def test_fused_mfma_operands_staged_or_not(Q, oracle, n5, n3, t):
     assert 1 - oracle.fidelity(ref, got) <= 1e-6
 
 
+@pytest.mark.parametrize("dtype,k,t", [(0, 6, 10), (0, 6, 12), (0, 6, 13), (0, 5, 12),
+                                       (1, 4, 12), (1, 5, 9), (1, 5, 11), (1, 5, 12)])
+def test_wide_dense_blocks_on_matrix_cores(Q, oracle, dtype, k, t):
+    """Dense blocks wider than the LDS-staged forms: complex64 6-qubit blocks
+    (128x128 real embedding, two M-tiles per wave) and complex128 4- and
+    5-qubit blocks in passes whose operands are not staged run on the matrix
+    cores in the wide kernel variant.  The pass features must count them as
+    MFMA blocks and none as a wide vector-ALU block; the state must match
+    the oracle."""
+    from paper_2509_04955_amd import costmodel
+
+    n = 15
+    rng = np.random.default_rng(1000 * dtype + 10 * k + t)
+
+    def unitary(m):
+        a = rng.normal(size=(1 << m, 1 << m)) + 1j * rng.normal(size=(1 << m, 1 << m))
+        return np.linalg.qr(a)[0]
+
+    c = qsynth.Circuit(n)
+    for _ in range(6):
+        qs = sorted(int(x) for x in rng.choice(n, size=k, replace=False))
+        c.add("dense", qs, (), unitary(k))
+        qs = sorted(int(x) for x in rng.choice(n, size=2, replace=False))
+        c.add("dense", qs, (), unitary(2))
+    plan = Q.qs_contract(n, Q.GateList(c), Q.opts(k_max=k, tile_qubits=t, dtype=dtype))
+    try:
+        f = costmodel.pass_features(plan)
+        assert f[:, 11].sum() == 0, "a dense block wider than 3 qubits ran on the vector ALU"
+        assert f[:, 8 if k == 4 else 9].sum() > 0, "no MFMA block of this width"
+    finally:
+        Q.qs_plan_destroy(plan)
+    psi0 = qsynth.random_state(n, seed=13)
+    ref = oracle.run(c, psi0.copy())
+    got, nrm = run_plan(Q, c, dtype, psi0, k_max=k, tile_qubits=t)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+    assert 1 - oracle.fidelity(ref, got) <= (1e-6 if dtype == 0 else 1e-12)
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_fused_k6_valu_and_wide_dense(Q, oracle, dtype):
     n = 12
