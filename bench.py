@@ -221,13 +221,16 @@ def learned_mode(a):
     progress(f"autotuned greedy: k_max {best.k_max}, t {best.tile_qubits}, low {best.low_qubits} ({tune_s:.0f} s)")
     train = []
     for nt in sorted({min(n, a.train_n - 1), min(n, a.train_n)}):
-        train += [qsynth.random_u3_cnot(nt, 6, seed=31), qsynth.ucc(nt, 30, seed=32)[0],
-                  qsynth.brickwork(nt, 6, seed=33), qsynth.hea(nt, 3, seed=(34, 0))]
+        train += [(qsynth.random_u3_cnot(nt, 6, seed=31), False), (qsynth.ucc(nt, 30, seed=32)[0], True),
+                  (qsynth.brickwork(nt, 6, seed=33), False), (qsynth.hea(nt, 3, seed=(34, 0)), False)]
     t0 = time.perf_counter()
     parts = []
-    for i, tc in enumerate(train):
+    for i, (tc, rot) in enumerate(train):
+        # circuits with Pauli rotations: also the passes of rotation-contracted plans
+        strategies = (Q.STRATEGY_GREEDY, Q.STRATEGY_PAULI) if rot else (Q.STRATEGY_GREEDY,)
         parts.append(CM.collect([tc], widths=(1, 2, 3, 4, 5, 6), tiles=(best.tile_qubits,),
-                                lows=tuple(sorted({best.low_qubits, 6})), reps=3, max_passes=24))
+                                lows=tuple(sorted({best.low_qubits, 6})), reps=3, max_passes=24,
+                                strategies=strategies))
         progress(f"timed passes of training circuit {i + 1}/{len(train)} ({tc.n} qubits)")
     X = np.concatenate([p[0] for p in parts])
     y = np.concatenate([p[1] for p in parts])
@@ -263,10 +266,29 @@ def learned_mode(a):
     ms_g5 = _timed(lambda: (st.set_basis(0), st.apply_plan(greedy5)))
     ms_l5 = _timed(lambda: (st.set_basis(0), st.apply_plan(learned5)))
     progress(f"k_max 5: greedy {ms_g5:.1f} ms, learned {ms_l5:.1f} ms")
-    ms_g = _timed(lambda: (st.set_basis(0), st.apply_plan(greedy)))
-    progress(f"greedy {ms_g:.1f} ms")
-    ms_l = _timed(lambda: (st.set_basis(0), st.apply_plan(learned)))
-    progress(f"learned {ms_l:.1f} ms")
+    # five timings of each plan, interleaved; medians and spread
+    runs_g, runs_l = [], []
+    for _ in range(5):
+        runs_g.append(_timed(lambda: (st.set_basis(0), st.apply_plan(greedy))))
+        runs_l.append(_timed(lambda: (st.set_basis(0), st.apply_plan(learned))))
+    ms_g, ms_l = float(np.median(runs_g)), float(np.median(runs_l))
+    progress(f"greedy {ms_g:.1f} ms [{min(runs_g):.1f}, {max(runs_g):.1f}], "
+             f"learned {ms_l:.1f} ms [{min(runs_l):.1f}, {max(runs_l):.1f}]")
+    # beside it, the rotation strategy in its own autotuned configuration
+    # (circuits with Pauli rotations only): what the learned plan is up against
+    # when the rotation rule is applied to the whole circuit
+    pauli = None
+    if a.circuit == "ucc":
+        bp = Q.qs_autotune(n, Q.QS_C64, Q.GateList(c.prefix(400)), Q.opts(strategy=Q.STRATEGY_PAULI, renorm=1))
+        pp = Q.qs_contract(n, gl, Q.opts(strategy=Q.STRATEGY_PAULI, k_max=bp.k_max, tile_qubits=bp.tile_qubits,
+                                         low_qubits=bp.low_qubits))
+        runs_p = [_timed(lambda: (st.set_basis(0), st.apply_plan(pp))) for _ in range(5)]
+        pauli = {"config": {"k_max": bp.k_max, "tile_qubits": bp.tile_qubits, "low_qubits": bp.low_qubits},
+                 "passes": int(Q.qs_plan_info_get(pp).n_passes), "ms": round(float(np.median(runs_p)), 2),
+                 "ms_range": [round(min(runs_p), 2), round(max(runs_p), 2)],
+                 "learned_gain_vs_it": round(float(np.median(runs_p)) / ms_l, 3)}
+        Q.qs_plan_destroy(pp)
+        progress(f"rotation strategy (autotuned) {pauli['ms']} ms, {pauli['passes']} passes")
     # same state from both schedules: fidelity over all amplitudes, streamed
     # to the host in chunks of 2^26 (two device states, bounded host memory)
     st.set_basis(0)
@@ -301,10 +323,11 @@ def learned_mode(a):
            "train_rows": int(len(y)), "train_loss": loss, "refine_s": round(refine_s, 1),
            "train_corr": corr, "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
            "greedy": {"passes": int(ig.n_passes), "blocks": int(ig.n_blocks), "ms": round(ms_g, 2),
-                      "plan_s": round(tg_plan, 2)},
+                      "ms_range": [round(min(runs_g), 2), round(max(runs_g), 2)], "plan_s": round(tg_plan, 2)},
            "learned": {"passes": int(il.n_passes), "blocks": int(il.n_blocks), "ms": round(ms_l, 2),
-                       "plan_s": round(tl_plan, 2)},
-           "gain": round(ms_g / ms_l, 3), "fidelity_learned_vs_greedy": fid,
+                       "ms_range": [round(min(runs_l), 2), round(max(runs_l), 2)], "plan_s": round(tl_plan, 2)},
+           "gain": round(ms_g / ms_l, 3), "gain_note": "median of 5 timings each, vs the autotuned greedy plan",
+           "rotation_strategy_autotuned": pauli, "fidelity_learned_vs_greedy": fid,
            "c_cdagger_zero_prob": abs(a0) ** 2, "norm_after_c_cdagger": norm_cc,
            "k_max5": {"greedy_ms": round(ms_g5, 2), "learned_ms": round(ms_l5, 2), "gain": round(ms_g5 / ms_l5, 3)}}
     Q.qs_plan_destroy(greedy5)

@@ -36,18 +36,21 @@ def time_passes(plan, dtype: int, reps: int = 3) -> np.ndarray:
 
 
 def collect(circuits, dtype: int = Q.QS_C64, widths=(1, 2, 3, 4, 5, 6), tiles=(12, 13), reps: int = 3,
-            max_passes: int = 64, lows=(0,)):
-    """Timing dataset over circuits x widths x tiles x fixed-low-qubit counts
-    (0 = the library default; the first `max_passes` passes of each plan are
-    timed).  Returns (X, target, us)."""
+            max_passes: int = 64, lows=(0,), strategies=(Q.STRATEGY_GREEDY,)):
+    """Timing dataset over circuits x strategies x widths x tiles x
+    fixed-low-qubit counts (0 = the library default; the first `max_passes`
+    passes of each plan are timed).  STRATEGY_PAULI adds the passes of
+    rotation-contracted plans (rotation blocks beside greedy blocks of each
+    width).  Returns (X, target, us)."""
     xs, ys = [], []
     for c in circuits:
         gl = Q.GateList(c)
-        for t, low, k in itertools.product(tiles, lows, widths):
+        for strat, t, low, k in itertools.product(strategies, tiles, lows, widths):
             if dtype == Q.QS_C128 and k > 5:
                 continue
             try:
-                plan = Q.qs_contract(c.n, gl, Q.opts(k_max=k, tile_qubits=t, low_qubits=low, dtype=dtype))
+                plan = Q.qs_contract(c.n, gl, Q.opts(k_max=k, tile_qubits=t, low_qubits=low, dtype=dtype,
+                                                     strategy=strat))
             except Q.QsimError:
                 continue
             try:

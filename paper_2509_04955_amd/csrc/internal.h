@@ -203,6 +203,14 @@ void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector
 // Pauli block on its support
 std::vector<PauliWindow> find_pauli_windows(const std::vector<HGate> &gates, int max_x_weight);
 void pauli_block_matrix(HBlock &b);
+// planner.cpp: the rotation windows the Pauli strategy contracts (X weight at
+// most max_x_weight; diagonal rotations no wider than k_max are left to the
+// greedy rule) and the blocks of that contraction: each window one rotation
+// block (members: the window's gate range), every other gate merged greedily
+// at k_max.  Members index `gates`; block matrices are not formed.
+std::vector<PauliWindow> pauli_windows(const std::vector<HGate> &gates, int k_max, int max_x_weight);
+void pauli_contract(const std::vector<HGate> &gates, int n, int k_max, const std::vector<PauliWindow> &win,
+                    std::vector<HBlock> &blocks);
 int default_tile(qs_dtype dt);
 // learned.cpp: features of one pass (kNumFeatures floats) and the learned
 // per-window partition

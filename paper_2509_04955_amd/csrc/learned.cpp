@@ -77,6 +77,7 @@ namespace {
 struct Candidate {
     int k = 0;                    // fusion width of this re-contraction
     int span = 1;                 // consecutive windows it covers
+    bool rot = false;             // Pauli-strategy contraction of the run
     std::vector<HBlock> blocks;   // member indices are global gate indices
     std::vector<HPass> passes;    // block0 relative to `blocks`
     double cost = 0;
@@ -86,8 +87,11 @@ struct Candidate {
 // fraction: the greedy plan is the fallback, and the model's error on a
 // single window is of that order.
 constexpr double kSwitchMargin = 0.03;
-// Longest run of consecutive greedy windows re-contracted as one candidate.
+// Longest run of consecutive greedy windows re-contracted as one candidate
+// (rotation candidates: a rotation's gates often straddle two or three
+// windows, so their runs may be longer).
 constexpr int kMaxSpan = 3;
+constexpr int kMaxSpanRot = 5;
 
 }  // namespace
 
@@ -109,20 +113,53 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
         std::sort(window[w].begin(), window[w].end());
     }
     // 2. candidates: runs of 1..kMaxSpan consecutive windows re-contracted
-    //    together at every width (the run's gates in program order)
+    //    together at every width (the run's gates in program order) and, when
+    //    the circuit holds Pauli rotations, runs of up to kMaxSpanRot windows
+    //    contracted as the Pauli strategy does (each rotation whose gates all
+    //    lie in the run one block, the rest greedily at k_max)
     int wgate = 1;
     for (const HGate &g : p.gates) wgate = std::max(wgate, g.nq);
+    // X parts must fit the tile's free slots beside the c low qubits
+    const int max_x = std::min(8, std::min(t, p.n) - c);
+    const bool rotations = max_x >= 1 && !pauli_windows(p.gates, o.k_max, max_x).empty();
+    const int span_max = rotations ? kMaxSpanRot : kMaxSpan;
     std::vector<std::vector<Candidate>> cand(nw);   // cand[e]: runs ending at window e
     std::vector<float> feats;
     std::vector<std::pair<size_t, size_t>> owner;  // (end window, candidate) of each feature row
     for (size_t e = 0; e < nw; ++e) {
-        for (int r = 1; r <= kMaxSpan && (size_t)r <= e + 1; ++r) {
+        for (int r = 1; r <= span_max && (size_t)r <= e + 1; ++r) {
             std::vector<int64_t> gids;
             for (size_t w = e + 1 - r; w <= e; ++w) gids.insert(gids.end(), window[w].begin(), window[w].end());
             std::sort(gids.begin(), gids.end());
             std::vector<HGate> sub;
             sub.reserve(gids.size());
             for (int64_t gi : gids) sub.push_back(p.gates[gi]);
+            if (rotations) {
+                const std::vector<PauliWindow> win = pauli_windows(sub, o.k_max, max_x);
+                if (!win.empty()) {
+                    Candidate cd;
+                    cd.k = o.k_max;
+                    cd.span = r;
+                    cd.rot = true;
+                    pauli_contract(sub, p.n, o.k_max, win, cd.blocks);
+                    for (HBlock &b : cd.blocks) {
+                        if (!b.pauli) block_matrix(sub, b);
+                        for (int64_t &m : b.members) m = gids[m];
+                    }
+                    pack_passes(p, cd.blocks, t, c, cd.passes);
+                    for (const HPass &ps : cd.passes) {
+                        feats.resize(feats.size() + kNumFeatures);
+                        pass_features(p.n, dt, ps, cd.blocks, feats.data() + feats.size() - kNumFeatures);
+                        owner.push_back({e, cand[e].size()});
+                    }
+                    for (HBlock &b : cd.blocks) {
+                        b.U.clear();
+                        b.U.shrink_to_fit();
+                    }
+                    cand[e].push_back(std::move(cd));
+                }
+            }
+            if (r > kMaxSpan) continue;
             for (int k = 1; k <= kcap; ++k) {
                 if (t < p.n && std::max(k, wgate) > t - 1) continue;
                 if (r > 1 && k == o.k_max) continue;   // the greedy width over several windows is the windows themselves
@@ -162,7 +199,7 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
         best[e + 1] = std::numeric_limits<double>::infinity();
         for (size_t i = 0; i < cand[e].size(); ++i) {
             const Candidate &cd = cand[e][i];
-            const bool greedy = cd.span == 1 && cd.k == o.k_max;
+            const bool greedy = cd.span == 1 && cd.k == o.k_max && !cd.rot;
             const double v = best[e + 1 - cd.span] + cd.cost * (greedy ? 1.0 : 1.0 / (1.0 - kSwitchMargin));
             if (v < best[e + 1]) {
                 best[e + 1] = v;
@@ -186,7 +223,7 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
             p.passes.push_back(std::move(ps));
         }
         for (HBlock &b : cd->blocks) {
-            block_matrix(p.gates, b);
+            if (!b.pauli) block_matrix(p.gates, b);
             p.blocks.push_back(std::move(b));
         }
     }

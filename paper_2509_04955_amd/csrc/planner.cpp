@@ -232,6 +232,60 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
     blocks.swap(ordered);
 }
 
+std::vector<PauliWindow> pauli_windows(const std::vector<HGate> &gates, int k_max, int max_x_weight) {
+    std::vector<PauliWindow> win = find_pauli_windows(gates, max_x_weight);
+    // a diagonal rotation (no X part) no wider than k_max is left to the
+    // greedy rule, which merges several of them (and their neighbours) into
+    // one diagonal block: one block per rotation would cost a tile round trip
+    // each (QAOA's ZZ terms)
+    win.erase(std::remove_if(win.begin(), win.end(),
+                             [&](const PauliWindow &w) { return w.x == 0 && (int)w.support.size() <= k_max; }),
+              win.end());
+    return win;
+}
+
+void pauli_contract(const std::vector<HGate> &gates, int n, int k_max, const std::vector<PauliWindow> &win,
+                    std::vector<HBlock> &blocks) {
+    // units: each window, and every gate outside the windows, in program
+    // order; a window is a block of its own, the gates merge greedily
+    std::vector<HGate> units;
+    std::vector<char> solo;
+    std::vector<int64_t> first;   // window: its index; gate: its program index
+    size_t wi = 0;
+    for (int64_t gi = 0; gi < (int64_t)gates.size();) {
+        if (wi < win.size() && win[wi].begin == gi) {
+            HGate u;
+            u.nq = (int)win[wi].support.size();
+            for (int j = 0; j < u.nq; ++j) u.q[j] = win[wi].support[j];
+            units.push_back(std::move(u));
+            solo.push_back(1);
+            first.push_back((int64_t)wi);
+            gi = win[wi].end;
+            ++wi;
+        } else {
+            units.push_back(gates[gi]);
+            solo.push_back(0);
+            first.push_back(gi);
+            ++gi;
+        }
+    }
+    greedy_blocks(units, n, k_max, blocks, &solo);
+    for (HBlock &b : blocks) {
+        if (b.members.size() == 1 && solo[b.members[0]]) {
+            const PauliWindow &w = win[first[b.members[0]]];
+            b.pauli = true;
+            b.px = w.x;
+            b.pz = w.z;
+            b.pc = w.c;
+            b.pd = w.d;
+            b.members.clear();
+            for (int64_t gi = w.begin; gi < w.end; ++gi) b.members.push_back(gi);
+        } else {
+            for (int64_t &m : b.members) m = first[m];
+        }
+    }
+}
+
 qs_status build_plan(qs_plan_s &p) {
     qs_contract_opts &o = p.opts;
     const qs_dtype dt = o.dtype == QS_C128 ? QS_C128 : QS_C64;
@@ -256,14 +310,7 @@ qs_status build_plan(qs_plan_s &p) {
     std::vector<PauliWindow> win;
     if (o.strategy == QS_STRATEGY_PAULI) {
         // X parts up to 8 qubits and below the tile (qubit 0 keeps a slot)
-        win = find_pauli_windows(p.gates, std::min(8, std::min(o.tile_qubits, p.n) - 1));
-        // a diagonal rotation (no X part) no wider than k_max is left to the
-        // greedy rule, which merges several of them (and their neighbours)
-        // into one diagonal block: one block per rotation would cost a tile
-        // round trip each (QAOA's ZZ terms)
-        win.erase(std::remove_if(win.begin(), win.end(),
-                                 [&](const PauliWindow &w) { return w.x == 0 && (int)w.support.size() <= o.k_max; }),
-                  win.end());
+        win = pauli_windows(p.gates, o.k_max, std::min(8, std::min(o.tile_qubits, p.n) - 1));
         for (const PauliWindow &w : win) wmax = std::max(wmax, __builtin_popcountll(w.x));
     }
     if (t < p.n)
@@ -283,44 +330,7 @@ qs_status build_plan(qs_plan_s &p) {
     } else if (o.strategy == QS_STRATEGY_LEARNED && costmodel_loaded()) {
         return learned_partition(p, t, c);
     } else if (o.strategy == QS_STRATEGY_PAULI) {
-        // units: each window, and every gate outside the windows, in program
-        // order; a window is a block of its own, the gates merge greedily
-        std::vector<HGate> units;
-        std::vector<char> solo;
-        std::vector<int64_t> first;   // window: its index; gate: its program index
-        size_t wi = 0;
-        for (int64_t gi = 0; gi < (int64_t)p.gates.size();) {
-            if (wi < win.size() && win[wi].begin == gi) {
-                HGate u;
-                u.nq = (int)win[wi].support.size();
-                for (int j = 0; j < u.nq; ++j) u.q[j] = win[wi].support[j];
-                units.push_back(std::move(u));
-                solo.push_back(1);
-                first.push_back((int64_t)wi);
-                gi = win[wi].end;
-                ++wi;
-            } else {
-                units.push_back(p.gates[gi]);
-                solo.push_back(0);
-                first.push_back(gi);
-                ++gi;
-            }
-        }
-        greedy_blocks(units, p.n, o.k_max, p.blocks, &solo);
-        for (HBlock &b : p.blocks) {
-            if (b.members.size() == 1 && solo[b.members[0]]) {
-                const PauliWindow &w = win[first[b.members[0]]];
-                b.pauli = true;
-                b.px = w.x;
-                b.pz = w.z;
-                b.pc = w.c;
-                b.pd = w.d;
-                b.members.clear();
-                for (int64_t gi = w.begin; gi < w.end; ++gi) b.members.push_back(gi);
-            } else {
-                for (int64_t &m : b.members) m = first[m];
-            }
-        }
+        pauli_contract(p.gates, p.n, o.k_max, win, p.blocks);
     } else {
         greedy_blocks(p.gates, p.n, o.k_max, p.blocks);
     }
