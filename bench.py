@@ -385,7 +385,8 @@ def families_mode(a):
     the autotuned width; time gate by gate (one sweep per gate), with every
     gate a block of its own streamed in the same tile passes (several gates
     per sweep, no contraction: the role of the paper's multi-gate ablation),
-    fused, and fused with Pauli-rotation contraction (strategy 3)."""
+    fused, fused with Pauli-rotation contraction (strategy 3), and fused with
+    commutation-aware contraction (the commute option, autotuned)."""
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
@@ -408,15 +409,22 @@ def families_mode(a):
             rot = Q.qs_contract(n, gl, Q.opts(k_max=best.k_max, tile_qubits=best.tile_qubits,
                                               low_qubits=best.low_qubits, strategy=Q.STRATEGY_PAULI))
             rinfo = Q.qs_plan_info_get(rot)
+            # commutation-aware contraction (commute option), autotuned on its own
+            best_c = Q.qs_autotune(n, Q.QS_C64, gl, Q.opts(strategy=Q.STRATEGY_GREEDY, renorm=1, commute=1))
+            com = Q.qs_contract(n, gl, Q.opts(k_max=best_c.k_max, tile_qubits=best_c.tile_qubits,
+                                              low_qubits=best_c.low_qubits, commute=1))
+            cinfo = Q.qs_plan_info_get(com)
             st = Q.State(n, Q.QS_C64)
             ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
             ms_multi = _timed(lambda: (st.set_basis(0), st.apply_plan(multi)))
             ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
             ms_rot = _timed(lambda: (st.set_basis(0), st.apply_plan(rot)))
+            ms_com = _timed(lambda: (st.set_basis(0), st.apply_plan(com)))
             st.close()
             Q.qs_plan_destroy(plan)
             Q.qs_plan_destroy(multi)
             Q.qs_plan_destroy(rot)
+            Q.qs_plan_destroy(com)
             S = 8 << n
             rows.append({"family": name, "n": n, "gates": len(c),
                          "compression_k2": round(1 - b2 / len(c), 4),
@@ -428,6 +436,9 @@ def families_mode(a):
                          "speedup": round(ms_plain / ms_fused, 2),
                          "rotation_passes": int(rinfo.n_passes), "rotation_ms": round(ms_rot, 2),
                          "rotation_speedup": round(ms_plain / ms_rot, 2),
+                         "commute_k_max": best_c.k_max, "commute_blocks": int(cinfo.n_blocks),
+                         "commute_passes": int(cinfo.n_passes), "commute_ms": round(ms_com, 2),
+                         "commute_gain_vs_fused": round(ms_fused / ms_com, 3),
                          "fused_gate_by_gate_equivalent_gbs": round(plain_bytes(c, S) / (ms_fused * 1e-3) / 1e9, 1)})
             print(f"[families] {rows[-1]}", file=sys.stderr, flush=True)
     print(json.dumps({"mode": "families", "rows": rows}), flush=True)

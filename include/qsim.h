@@ -98,7 +98,12 @@ typedef struct {
     int32_t strategy;     /* QS_STRATEGY_* */
     int32_t renorm;       /* 1: FP64 norm of every pass, next pass rescales by 1/sqrt(norm) */
     int32_t dtype;        /* qs_dtype the plan is costed for (learned strategy); default c64 */
-    int32_t reserved[2];
+    int32_t commute;      /* 1: a gate may be contracted past earlier gates it commutes with, i.e.
+                             gates diagonal (commuting with Z) on every qubit they share, such as
+                             phase and CZ gates with each other or with a CNOT's control; 0: every
+                             pair of gates sharing a qubit keeps its order (Section 3.4's DAG).
+                             Applies to the greedy contraction of every strategy. */
+    int32_t reserved;
 } qs_contract_opts;
 
 typedef struct {

@@ -98,6 +98,124 @@ def check_order(gates, blocks: Sequence[Sequence[int]]) -> None:
             last_on[q] = gi
 
 
+def diagonal_qubits(gates, gi: int) -> set:
+    """Qubits on which gate gi acts diagonally: its matrix on its own qubits
+    has no nonzero entry between basis states that differ in that qubit
+    (it commutes with Z there; controls of controlled gates and every qubit
+    of a phase or CZ gate are such qubits)."""
+    U = block_matrix(gates, [gi])
+    qs = block_qubits(gates, [gi])
+    rows, cols = np.nonzero(U)
+    return {q for j, q in enumerate(qs) if not np.any(((rows ^ cols) >> j) & 1)}
+
+
+def greedy_commute(gates, k_max: int) -> List[List[int]]:
+    """GREEDY-FW(k_max) with commutation (beyond Section 3.4's DAG, which
+    orders every pair of gates sharing a qubit).
+
+    Two gates that are both diagonal on every qubit they share commute: with
+    S the shared qubits, each is a sum over basis states s of S of the
+    projector |s><s| times an operator on its other qubits, and those other
+    operators act on disjoint qubits.  So gate g need only follow the
+    earlier gates that act non-diagonally on a qubit g is diagonal on, and
+    every earlier gate on a qubit g acts on non-diagonally:
+
+      f = max over q in Q_g of (last_nd[q] if g is diagonal on q else last[q]),
+
+    g goes into the lowest existing block j >= max(f, 1) with
+    |Q_Bj u Q_g| <= k_max, else into a new block; then last[q] and, where g
+    is not diagonal on q, last_nd[q] become max(old, j).  Blocks in index
+    order then put every pair of non-commuting gates in program order."""
+    last, last_nd = {}, {}
+    blocks: List[List[int]] = []
+    qsets: List[set] = []
+    for gi, g in enumerate(gates):
+        Q = set(g.qubits)
+        D = diagonal_qubits(gates, gi)
+        f = max(((last_nd if q in D else last).get(q, 0) for q in Q), default=0)
+        j = None
+        if len(Q) <= k_max:
+            for cand in range(max(f, 1), len(blocks) + 1):
+                if len(qsets[cand - 1] | Q) <= k_max:
+                    j = cand
+                    break
+        if j is None:
+            blocks.append([])
+            qsets.append(set())
+            j = len(blocks)
+        blocks[j - 1].append(gi)
+        qsets[j - 1] |= Q
+        for q in Q:
+            last[q] = max(last.get(q, 0), j)
+            if q not in D:
+                last_nd[q] = max(last_nd.get(q, 0), j)
+    return blocks
+
+
+def check_order_commute(gates, blocks: Sequence[Sequence[int]]) -> None:
+    """Like check_order, except that two gates may swap when both are
+    diagonal on every qubit they share (they commute); every gate appears
+    exactly once."""
+    where = {}
+    for b, members in enumerate(blocks):
+        for pos, gi in enumerate(members):
+            assert gi not in where, f"gate {gi} in two blocks"
+            where[gi] = (b, pos)
+    assert sorted(where) == list(range(len(gates))), "gates missing from plan"
+    diag = [diagonal_qubits(gates, gi) for gi in range(len(gates))]
+    on = {}
+    for gi, g in enumerate(gates):
+        for q in g.qubits:
+            on.setdefault(q, []).append(gi)
+    for q, seq in on.items():
+        for i, a in enumerate(seq):
+            for b in seq[i + 1:]:
+                if where[a] > where[b]:
+                    shared = set(gates[a].qubits) & set(gates[b].qubits)
+                    assert all(s in diag[a] and s in diag[b] for s in shared), \
+                        f"gates {a} and {b} swapped on qubit {q} without commuting"
+
+
+def block_diagonal_qubits(U: np.ndarray, qubits, tol: float = 1e-14) -> set:
+    """Qubits on which a block matrix (local bit j <-> qubits[j]) acts
+    diagonally, entries below tol counting as zero (rounding residue of the
+    product's exact zeros)."""
+    rows, cols = np.nonzero(np.abs(U) > tol)
+    return {q for j, q in enumerate(qubits) if not np.any(((rows ^ cols) >> j) & 1)}
+
+
+def check_block_order_commute(gates, blocks: Sequence[Sequence[int]], qubit_lists, matrices) -> None:
+    """Plan checker for plans whose blocks were reordered by commutation:
+    every gate appears exactly once, and every pair of gates sharing a qubit
+    whose program order the block order reverses either commutes itself (both
+    gates diagonal on every qubit they share) or lies in two blocks that are
+    both diagonal on every qubit the two blocks share."""
+    where = {}
+    for b, members in enumerate(blocks):
+        for pos, gi in enumerate(members):
+            assert gi not in where, f"gate {gi} in two blocks"
+            where[gi] = (b, pos)
+    assert sorted(where) == list(range(len(gates))), "gates missing from plan"
+    gdiag = [diagonal_qubits(gates, gi) for gi in range(len(gates))]
+    bdiag = [block_diagonal_qubits(U, qs) for qs, U in zip(qubit_lists, matrices)]
+    on = {}
+    for gi, g in enumerate(gates):
+        for q in g.qubits:
+            on.setdefault(q, []).append(gi)
+    for q, seq in on.items():
+        for i, a in enumerate(seq):
+            for b in seq[i + 1:]:
+                if where[a] < where[b]:
+                    continue
+                shared = set(gates[a].qubits) & set(gates[b].qubits)
+                if all(s in gdiag[a] and s in gdiag[b] for s in shared):
+                    continue
+                ba, bb = where[a][0], where[b][0]
+                bshared = set(qubit_lists[ba]) & set(qubit_lists[bb])
+                assert all(s in bdiag[ba] and s in bdiag[bb] for s in bshared), \
+                    f"gates {a} and {b} swapped on qubit {q} without commuting"
+
+
 def apply_blocks(psi: np.ndarray, n: int, qubit_lists, matrices) -> np.ndarray:
     """Apply block matrices in order with the oracle's dense routine."""
     for qs, U in zip(qubit_lists, matrices):

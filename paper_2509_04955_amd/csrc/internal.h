@@ -195,9 +195,16 @@ bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt
 // packs blocks into passes and reorders them into execution order (in place)
 void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c,
                  std::vector<HPass> &out);
-// solo (optional): units that always form a block of their own
+// solo (optional): units that always form a block of their own.  commute: a
+// gate only follows the earlier gates it may not commute with (those acting
+// non-diagonally on a qubit it shares, or any gate sharing a qubit it acts on
+// non-diagonally); without it every gate follows all earlier gates sharing a
+// qubit (Section 3.4's DAG)
 void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks,
-                   const std::vector<char> *solo = nullptr);
+                   const std::vector<char> *solo = nullptr, bool commute = false);
+// qubits on which a gate acts diagonally (its matrix has no entry between
+// basis states that differ in that qubit); 0 for a gate without a matrix
+uint64_t diagonal_qubits(const HGate &g);
 // pauli.cpp: windows of Clifford gates around one diagonal one-qubit gate whose
 // Clifford parts cancel (X weight at most max_x_weight); dense matrix of a
 // Pauli block on its support
@@ -210,7 +217,7 @@ void pauli_block_matrix(HBlock &b);
 // at k_max.  Members index `gates`; block matrices are not formed.
 std::vector<PauliWindow> pauli_windows(const std::vector<HGate> &gates, int k_max, int max_x_weight);
 void pauli_contract(const std::vector<HGate> &gates, int n, int k_max, const std::vector<PauliWindow> &win,
-                    std::vector<HBlock> &blocks);
+                    std::vector<HBlock> &blocks, bool commute = false);
 int default_tile(qs_dtype dt);
 // learned.cpp: features of one pass (kNumFeatures floats) and the learned
 // per-window partition

@@ -102,7 +102,7 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
     if (t < p.n) kcap = std::min(kcap, t - 1);
     // 1. reference windows
     std::vector<HBlock> ref;
-    greedy_blocks(p.gates, p.n, o.k_max, ref);
+    greedy_blocks(p.gates, p.n, o.k_max, ref, nullptr, o.commute != 0);
     std::vector<HPass> ref_passes;
     pack_passes(p, ref, t, c, ref_passes);
     const size_t nw = ref_passes.size();
@@ -141,7 +141,7 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
                     cd.k = o.k_max;
                     cd.span = r;
                     cd.rot = true;
-                    pauli_contract(sub, p.n, o.k_max, win, cd.blocks);
+                    pauli_contract(sub, p.n, o.k_max, win, cd.blocks, o.commute != 0);
                     for (HBlock &b : cd.blocks) {
                         if (!b.pauli) block_matrix(sub, b);
                         for (int64_t &m : b.members) m = gids[m];
@@ -166,7 +166,7 @@ qs_status learned_partition(qs_plan_s &p, int t, int c) {
                 Candidate cd;
                 cd.k = k;
                 cd.span = r;
-                greedy_blocks(sub, p.n, k, cd.blocks);
+                greedy_blocks(sub, p.n, k, cd.blocks, nullptr, o.commute != 0);
                 for (HBlock &b : cd.blocks) {
                     block_matrix(sub, b);   // for the block kinds in the features; dropped below
                     for (int64_t &m : b.members) m = gids[m];

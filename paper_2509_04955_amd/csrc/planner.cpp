@@ -57,30 +57,54 @@ struct MinTree {
 
 }  // namespace
 
+uint64_t diagonal_qubits(const HGate &g) {
+    if (g.m.empty()) return 0;
+    const int d = 1 << g.nq;
+    uint64_t out = 0;
+    for (int j = 0; j < g.nq; ++j) {
+        bool diag = true;
+        for (int r = 0; r < d && diag; ++r)
+            for (int c = 0; c < d; ++c)
+                if (((r ^ c) >> j) & 1 && g.m[(size_t)r * d + c] != cd(0, 0)) {
+                    diag = false;
+                    break;
+                }
+        if (diag) out |= 1ull << g.q[j];
+    }
+    return out;
+}
+
 void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector<HBlock> &blocks,
-                   const std::vector<char> *solo) {
+                   const std::vector<char> *solo, bool commute) {
     blocks.clear();
     std::vector<int> last(n, 0);                 // 1-based block index, 0 = none
+    std::vector<int> last_nd(n, 0);              // latest block acting non-diagonally on the qubit
     std::vector<uint64_t> qmask;                 // qubit mask per block
     std::vector<int> width;
     std::vector<char> closed;                    // blocks that take no further gates (solo units)
     MinTree tree(gates.size() + 1);
     for (size_t gi = 0; gi < gates.size(); ++gi) {
         const HGate &g = gates[gi];
+        const uint64_t dq = commute ? diagonal_qubits(g) : 0;
         uint64_t gm = 0;
-        int f = 0;
+        int f = 0, L = 0;   // f: latest block g must follow; L: latest block touching g's qubits
         for (int j = 0; j < g.nq; ++j) {
-            gm |= 1ull << g.q[j];
-            f = std::max(f, last[g.q[j]]);
+            const int q = g.q[j];
+            gm |= 1ull << q;
+            f = std::max(f, ((dq >> q) & 1) ? last_nd[q] : last[q]);
+            L = std::max(L, last[q]);
         }
         const int w = g.nq;
         const bool alone = solo && (*solo)[gi];
         int j = -1;  // 1-based
         if (w <= kmax && !alone) {
-            if (f >= 1 && !closed[f - 1] && __builtin_popcountll(qmask[f - 1] | gm) <= kmax) {
-                j = f;
-            } else {
-                int idx = tree.first_le(std::max(f + 1, 1), kmax - w);  // tree index = 1-based block id
+            // lowest block >= max(f, 1) whose qubits with g's stay within kmax:
+            // blocks up to L may share qubits with g (only when it commutes
+            // past them), blocks after L share none (width test in the tree)
+            for (int b = std::max(f, 1); b <= L && j < 0; ++b)
+                if (!closed[b - 1] && __builtin_popcountll(qmask[b - 1] | gm) <= kmax) j = b;
+            if (j < 0) {
+                int idx = tree.first_le(std::max(L + 1, 1), kmax - w);  // tree index = 1-based block id
                 if (idx >= 1 && idx <= (int)blocks.size()) j = idx;
             }
         }
@@ -95,7 +119,11 @@ void greedy_blocks(const std::vector<HGate> &gates, int n, int kmax, std::vector
         qmask[j - 1] |= gm;
         width[j - 1] = __builtin_popcountll(qmask[j - 1]);
         tree.set(j, closed[j - 1] ? 64 : width[j - 1]);
-        for (int q = 0; q < g.nq; ++q) last[g.q[q]] = j;
+        for (int q = 0; q < g.nq; ++q) {
+            const int qq = g.q[q];
+            last[qq] = std::max(last[qq], j);
+            if (!((dq >> qq) & 1)) last_nd[qq] = std::max(last_nd[qq], j);
+        }
     }
     for (size_t b = 0; b < blocks.size(); ++b) {
         blocks[b].qubits.clear();
@@ -156,6 +184,30 @@ void block_matrix(const std::vector<HGate> &gates, HBlock &b) {
 // share a qubit in program order, hence the same state in exact arithmetic.
 constexpr size_t kLookahead = 64;
 
+namespace {
+// entries of a block product below this are rounding residue of exact zeros
+// (the same threshold as the monomial test of the tile kernels)
+constexpr double kDiagTol = 1e-14;
+
+// qubits on which a (non-rotation) block acts diagonally, from its matrix
+uint64_t block_diagonal(const HBlock &b) {
+    const int k = (int)b.qubits.size(), d = 1 << k;
+    if (b.U.size() != (size_t)d * d) return 0;
+    uint64_t out = 0;
+    for (int j = 0; j < k; ++j) {
+        bool diag = true;
+        for (int r = 0; r < d && diag; ++r)
+            for (int c = 0; c < d; ++c)
+                if (((r ^ c) >> j) & 1 && std::abs(b.U[(size_t)r * d + c]) > kDiagTol) {
+                    diag = false;
+                    break;
+                }
+        if (diag) out |= 1ull << b.qubits[j];
+    }
+    return out;
+}
+}  // namespace
+
 void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, std::vector<HPass> &out) {
     out.clear();
     const int n = p.n;
@@ -172,11 +224,22 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
     }
     // Two Pauli-rotation blocks whose strings commute commute as operators
     // (each is c I + d P), so one may overtake the other although they share
-    // qubits; every other pair sharing a qubit keeps its order.
+    // qubits.  With the commute option, so may two blocks that are both
+    // diagonal on every qubit they share (dg: qubits a block acts on
+    // diagonally, from its matrix with entries below kDiagTol taken as the
+    // rounding residue of exact zeros; a rotation is diagonal off its X
+    // part).  Every other pair sharing a qubit keeps its order.
+    const bool by_diag = p.opts.commute != 0;
+    std::vector<uint64_t> dg(blocks.size(), 0);
+    if (by_diag)
+        for (size_t b = 0; b < blocks.size(); ++b) dg[b] = blocks[b].pauli ? dm[b] & ~blocks[b].px : block_diagonal(blocks[b]);
     auto commute = [&](size_t a, size_t b) {
         const HBlock &A = blocks[a], &B = blocks[b];
-        return A.pauli && B.pauli &&
-               ((__builtin_popcountll(A.px & B.pz) + __builtin_popcountll(A.pz & B.px)) & 1) == 0;
+        if (A.pauli && B.pauli &&
+            ((__builtin_popcountll(A.px & B.pz) + __builtin_popcountll(A.pz & B.px)) & 1) == 0)
+            return true;
+        const uint64_t shared = dm[a] & dm[b];
+        return by_diag && (shared & ~(dg[a] & dg[b])) == 0;
     };
     std::vector<size_t> pending(blocks.size()), rest;
     for (size_t b = 0; b < blocks.size(); ++b) pending[b] = b;
@@ -193,7 +256,7 @@ void pack_passes(const qs_plan_s &p, std::vector<HBlock> &blocks, int t, int c, 
             if (skipped && scanned_after_skip++ >= kLookahead) break;
             const size_t b = pending[i];
             bool free = (dm[b] & blocked) == 0;
-            if (!free && blocks[b].pauli) {
+            if (!free && (blocks[b].pauli || by_diag)) {
                 // overtaking is allowed past skipped blocks it commutes with
                 free = true;
                 for (size_t r : rest)
@@ -245,7 +308,7 @@ std::vector<PauliWindow> pauli_windows(const std::vector<HGate> &gates, int k_ma
 }
 
 void pauli_contract(const std::vector<HGate> &gates, int n, int k_max, const std::vector<PauliWindow> &win,
-                    std::vector<HBlock> &blocks) {
+                    std::vector<HBlock> &blocks, bool commute) {
     // units: each window, and every gate outside the windows, in program
     // order; a window is a block of its own, the gates merge greedily
     std::vector<HGate> units;
@@ -269,7 +332,7 @@ void pauli_contract(const std::vector<HGate> &gates, int n, int k_max, const std
             ++gi;
         }
     }
-    greedy_blocks(units, n, k_max, blocks, &solo);
+    greedy_blocks(units, n, k_max, blocks, &solo, commute);
     for (HBlock &b : blocks) {
         if (b.members.size() == 1 && solo[b.members[0]]) {
             const PauliWindow &w = win[first[b.members[0]]];
@@ -305,6 +368,7 @@ qs_status build_plan(qs_plan_s &p) {
     // tile and tiles start with a contiguous run.
     QS_CHECK(o.strategy >= QS_STRATEGY_NONE && o.strategy <= QS_STRATEGY_PAULI, QS_EINVAL, "strategy %d unknown",
              o.strategy);
+    QS_CHECK(o.commute == 0 || o.commute == 1, QS_EINVAL, "commute must be 0 or 1 (got %d)", o.commute);
     int wmax = o.k_max;
     for (const HGate &g : p.gates) wmax = std::max(wmax, g.nq);
     std::vector<PauliWindow> win;
@@ -330,9 +394,9 @@ qs_status build_plan(qs_plan_s &p) {
     } else if (o.strategy == QS_STRATEGY_LEARNED && costmodel_loaded()) {
         return learned_partition(p, t, c);
     } else if (o.strategy == QS_STRATEGY_PAULI) {
-        pauli_contract(p.gates, p.n, o.k_max, win, p.blocks);
+        pauli_contract(p.gates, p.n, o.k_max, win, p.blocks, o.commute != 0);
     } else {
-        greedy_blocks(p.gates, p.n, o.k_max, p.blocks);
+        greedy_blocks(p.gates, p.n, o.k_max, p.blocks, nullptr, o.commute != 0);
     }
     for (HBlock &b : p.blocks)
         if (!b.pauli) block_matrix(p.gates, b);

@@ -42,7 +42,7 @@ class qs_gate(ctypes.Structure):
 class qs_contract_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
                 ("strategy", ctypes.c_int32), ("renorm", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("commute", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class qs_plan_info(ctypes.Structure):
@@ -163,10 +163,10 @@ class GateList:
         return ctypes.cast(self.arr, ctypes.c_void_p)
 
 
-def opts(k_max=0, tile_qubits=0, low_qubits=0, strategy=STRATEGY_GREEDY, renorm=1, dtype=QS_C64):
+def opts(k_max=0, tile_qubits=0, low_qubits=0, strategy=STRATEGY_GREEDY, renorm=1, dtype=QS_C64, commute=0):
     o = qs_contract_opts()
     o.k_max, o.tile_qubits, o.low_qubits = k_max, tile_qubits, low_qubits
-    o.strategy, o.renorm, o.dtype = strategy, renorm, dtype
+    o.strategy, o.renorm, o.dtype, o.commute = strategy, renorm, dtype, commute
     return o
 
 

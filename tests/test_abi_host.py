@@ -428,3 +428,70 @@ def test_pauli_plan_tiles_hold_x_supports(Q, t):
         assert nxt == info.n_blocks
     finally:
         Q.qs_plan_destroy(plan)
+
+
+# ---- commutation-aware contraction (the commute option) ----------------------
+
+PHASE_HEAVY = ["cx", "cz", "rz", "t", "h", "cp", "rx", "s", "u3"]
+
+
+@pytest.mark.parametrize("k_max", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_commute_membership_matches_oracle(Q, k_max, seed):
+    """Block membership under the commute option equals the oracle's
+    commutation-aware rule exactly (integer work)."""
+    c = qsynth.random_circuit(11, 180, seed=seed, kinds=PHASE_HEAVY)
+    plan, _ = _plan(Q, c, k_max=k_max, tile_qubits=10, commute=1)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        got = sorted(tuple(Q.qs_plan_block(plan, b, False)[2]) for b in range(info.n_blocks))
+    finally:
+        Q.qs_plan_destroy(plan)
+    assert got == sorted(tuple(b) for b in greedy.greedy_commute(c.gates, k_max))
+
+
+@pytest.mark.parametrize("family", ["qft", "qaoa", "phase"])
+@pytest.mark.parametrize("k_max", [2, 3, 4])
+def test_commute_plan_replays_exactly(Q, oracle, family, k_max):
+    """Plan checker for commute plans (blocks also reordered by the pass
+    packer where they commute): every reversed pair of gates commutes itself
+    or sits in two blocks diagonal on every qubit they share, and the block
+    matrices in plan order reproduce the oracle's state from a random state."""
+    n = 11
+    c = {"qft": lambda: qsynth.qft(n), "qaoa": lambda: qsynth.qaoa_maxcut(n),
+         "phase": lambda: qsynth.random_circuit(n, 200, seed=k_max, kinds=PHASE_HEAVY)}[family]()
+    plan, _ = _plan(Q, c, k_max=k_max, tile_qubits=8, low_qubits=2, commute=1)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        qls, mats, mems = [], [], []
+        for b in range(info.n_blocks):
+            qs, U, mem = Q.qs_plan_block(plan, b)
+            qls.append(qs)
+            mats.append(U)
+            mems.append(mem)
+    finally:
+        Q.qs_plan_destroy(plan)
+    greedy.check_block_order_commute(c.gates, mems, qls, mats)
+    psi0 = qsynth.random_state(n, seed=3)
+    ref = oracle.run(c, psi0.copy())
+    got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_commute_needs_fewer_passes_on_qft(Q):
+    """30-qubit QFT at t = 13: its controlled phases commute with each other,
+    so the commute option packs them into fewer passes (20 against 25 at
+    k_max 4, 27 against 34 at k_max 3)."""
+    c = qsynth.qft(30)
+    for k, want in ((3, (27, 34)), (4, (20, 25))):
+        got = []
+        for cm in (1, 0):
+            plan, _ = _plan(Q, c, k_max=k, tile_qubits=13, low_qubits=4, commute=cm)
+            got.append(int(Q.qs_plan_info_get(plan).n_passes))
+            Q.qs_plan_destroy(plan)
+        assert tuple(got) == want
+
+
+def test_commute_flag_validated(Q):
+    with pytest.raises(Q.QsimError):
+        _plan(Q, qsynth.ghz(6), commute=2)

@@ -492,3 +492,24 @@ def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
     got, _ = run_plan(Q, c, 0, psi0, k_max=4, tile_qubits=t, low_qubits=4)
     assert oracle.max_abs(ref, got) <= TOL64
     assert 1 - oracle.fidelity(ref, got) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("family", ["qft", "qaoa", "phase"])
+@pytest.mark.parametrize("k_max,t", [(3, 12), (4, 13), (5, 12)])
+def test_commute_plans_match_oracle(Q, oracle, dtype, family, k_max, t):
+    """Plans contracted with the commute option (gates, and in the packer
+    whole blocks, passing others they commute with) give the oracle's state:
+    QFT (commuting controlled phases), QAOA and a phase-heavy random circuit
+    at 18 qubits, both precisions."""
+    if dtype == 1 and t > 12:
+        pytest.skip("complex128 tiles stop at t = 12")
+    n = 18
+    c = {"qft": lambda: qsynth.qft(n), "qaoa": lambda: qsynth.qaoa_maxcut(n),
+         "phase": lambda: qsynth.random_circuit(n, 400, seed=k_max,
+                                                kinds=["cx", "cz", "rz", "t", "h", "cp", "rx", "s", "u3"])}[family]()
+    psi0 = qsynth.random_state(n, seed=5)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=k_max, tile_qubits=t, low_qubits=4, commute=1)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+    assert 1 - oracle.fidelity(ref, got) <= (1e-6 if dtype == 0 else 1e-12)
