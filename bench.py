@@ -403,7 +403,10 @@ def families_mode(a):
     gate a block of its own streamed in the same tile passes (several gates
     per sweep, no contraction: the role of the paper's multi-gate ablation),
     fused, fused with Pauli-rotation contraction (strategy 3), and fused with
-    commutation-aware contraction (the commute option, autotuned)."""
+    commutation-aware contraction (the commute option, autotuned); and the
+    literal staggered multi-gate form (DAG layers of gates over cyclically
+    assigned state segments, qs_apply_gates_smgp), the paper's own ablation
+    against gate by gate."""
     import qsynth
     from paper_2509_04955_amd import qsim as Q
 
@@ -433,6 +436,7 @@ def families_mode(a):
             cinfo = Q.qs_plan_info_get(com)
             st = Q.State(n, Q.QS_C64)
             ms_plain = _timed(lambda: (st.set_basis(0), st.apply_gates(gl)))
+            ms_smgp = _timed(lambda: (st.set_basis(0), st.apply_gates_smgp(gl)))
             ms_multi = _timed(lambda: (st.set_basis(0), st.apply_plan(multi)))
             ms_fused = _timed(lambda: (st.set_basis(0), st.apply_plan(plan)))
             ms_rot = _timed(lambda: (st.set_basis(0), st.apply_plan(rot)))
@@ -447,7 +451,9 @@ def families_mode(a):
                          "compression_k2": round(1 - b2 / len(c), 4),
                          "k_max": best.k_max, "blocks": int(info.n_blocks),
                          "compression": round(1 - info.n_blocks / len(c), 4), "passes": int(info.n_passes),
-                         "plain_ms": round(ms_plain, 2), "multi_gate_ms": round(ms_multi, 2),
+                         "plain_ms": round(ms_plain, 2),
+                         "smgp_ms": round(ms_smgp, 2), "smgp_speedup": round(ms_plain / ms_smgp, 2),
+                         "multi_gate_ms": round(ms_multi, 2),
                          "multi_gate_passes": int(minfo.n_passes),
                          "multi_gate_speedup": round(ms_plain / ms_multi, 2), "fused_ms": round(ms_fused, 2),
                          "speedup": round(ms_plain / ms_fused, 2),

@@ -153,6 +153,17 @@ qs_status qs_norm(qs_state s, double *out);
  * the state is unchanged.  Asynchronous on the state's stream. */
 qs_status qs_apply_gates(qs_state s, const qs_gate *gates, size_t n_gates);
 
+/* The same circuit with staggered multi-gate parallelism (Section 3.3, the
+ * two-dimensional thread mapping and Table "segment"): the gates are grouped
+ * into DAG layers (gates of a layer share no qubit); the one-qubit and
+ * controlled one-qubit gates of a layer, up to 32 at a time, run in 2^s launches
+ * over 2^s state segments chosen by s qubits none of them touches, gate i
+ * updating segment (i + j) mod 2^s at step j; other gates run as in
+ * qs_apply_gates.  Every gate still sweeps the amplitudes it touches once.
+ * Same state as qs_apply_gates up to rounding order; validation, errors and
+ * asynchrony as there. */
+qs_status qs_apply_gates_smgp(qs_state s, const qs_gate *gates, size_t n_gates);
+
 /* -------------------------------------------------- contraction (host) */
 /* Build a plan for an n-qubit circuit: the dependency DAG of Section 3.4
  * (gates sharing a qubit keep program order), blocks merged under the chosen

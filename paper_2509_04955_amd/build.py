@@ -29,6 +29,7 @@ SOURCES = [
     "kernels_plain.hip",
     "kernels_tile.hip",
     "kernels_expect.hip",
+    "kernels_smgp.hip",
     "batch.hip",
     "mlp.hip",
     "autotune.cpp",

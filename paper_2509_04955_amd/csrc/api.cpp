@@ -291,6 +291,18 @@ qs_status qs_apply_gates(qs_state s, const qs_gate *gates, size_t n_gates) {
     QS_ABI_CATCH
 }
 
+qs_status qs_apply_gates_smgp(qs_state s, const qs_gate *gates, size_t n_gates) {
+    QS_ABI_TRY
+    QS_CHECK(s != nullptr, QS_EINVAL, "null state");
+    std::vector<HGate> hg;
+    qs_status st = convert_gates(s->n, gates, n_gates, hg);
+    if (st != QS_OK) return st;
+    st = materialize(*s);
+    if (st != QS_OK) return st;
+    return launch_smgp(*s, hg);
+    QS_ABI_CATCH
+}
+
 qs_status qs_contract(int n, const qs_gate *gates, size_t n_gates, const qs_contract_opts *opts, qs_plan *out) {
     QS_CHECK(out != nullptr, QS_EINVAL, "null output handle");
     QS_CHECK(n >= 1 && n <= kMaxQubits, QS_EINVAL, "n=%d outside 1..%d", n, kMaxQubits);

@@ -234,6 +234,8 @@ qs_status costmodel_predict_device(const float *features, int n_rows, float *out
 // kernels_plain.hip
 struct Mat2 { double re[4], im[4]; };
 qs_status launch_plain(qs_state_s &s, const HGate &g);
+// kernels_smgp.hip: the gates in DAG layers with staggered multi-gate launches
+qs_status launch_smgp(qs_state_s &s, const std::vector<HGate> &gates);
 qs_status launch_scale(qs_state_s &s, const double *d_scale);
 qs_status launch_set_basis(qs_state_s &s, uint64_t index);
 qs_status launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);

@@ -65,6 +65,35 @@ __device__ __forceinline__ void st_nt(V *p, V v) {
     __builtin_nontemporal_store(v, p);
 }
 
+// A double moved between lanes by a DPP pattern within rows of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (every lane active), the same value in
+// every lane, in a fixed order: within each row of 16 lanes by DPP moves
+// (lane ^ 1, lane ^ 2, mirror within 8, mirror within 16; after each step
+// partner lanes hold the same sum, IEEE addition being commutative), then the
+// four row sums read from lanes 0, 16, 32, 48.  No LDS traffic and no waits.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Tile index li of 16-byte vector vi = tid + NT*j (NT threads per workgroup)
 // splits into a per-thread part (tid*APV, below NT*APV) and a per-j part
 // (j*NT*APV); both the global
@@ -233,22 +262,29 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
         }
         // ---- store + FP64 norm partial ----
         double nacc = 0.0;
-        if (active) {
+        auto norm_of = [](const V &v) -> double {
+            if constexpr (F32) return (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+            else return v.x * v.x + v.y * v.y;
+        };
+        if constexpr (NJ > 0) {
+            // every LDS read issued before the first store: one wait chain
+            // instead of a read latency per stored vector
+            V vals[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) vals[j] = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * NT * APV)));
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                st_nt(gaddr(base, j), vals[j]);
+                nacc += norm_of(vals[j]);
+            }
+        } else if (active) {
             for (uint32_t j = 0; j < nj; ++j) {
                 const V v = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * NT * APV)));
                 st_nt(gaddr(base, j), v);
-                if constexpr (F32) {
-                    nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
-                } else {
-                    nacc += v.x * v.x + v.y * v.y;
-                }
+                nacc += norm_of(v);
             }
         }
-        if (pa.want_norm) {
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) nacc += __shfl_xor(nacc, o);
-            red[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)] = nacc;   // every lane holds the wave sum
-        }
+        if (pa.want_norm) red[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)] = wave_sum_f64(nacc);
         __syncthreads();  // every read of this tile from LDS is done, every norm slot written
         // Thread 0 sums the slots after that barrier; they are written again
         // only in the next tile's store phase, behind the loop-top barrier

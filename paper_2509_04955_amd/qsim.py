@@ -73,6 +73,7 @@ _SIGS = {
     "qs_state_copy_in": ([_vp, _u64, _u64, _vp], _i32),
     "qs_norm": ([_vp, _vp], _i32),
     "qs_apply_gates": ([_vp, _vp, ctypes.c_size_t], _i32),
+    "qs_apply_gates_smgp": ([_vp, _vp, ctypes.c_size_t], _i32),
     "qs_contract": ([_i32, _vp, ctypes.c_size_t, _vp, _vp], _i32),
     "qs_plan_destroy": ([_vp], _i32),
     "qs_plan_info_get": ([_vp, _vp], _i32),
@@ -219,6 +220,10 @@ def qs_norm(h) -> float:
 
 def qs_apply_gates(h, gl: GateList):
     _check(lib().qs_apply_gates(h, gl.ptr, gl.count))
+
+
+def qs_apply_gates_smgp(h, gl: GateList):
+    _check(lib().qs_apply_gates_smgp(h, gl.ptr, gl.count))
 
 
 def qs_contract(n: int, gl: GateList, o: qs_contract_opts | None = None):
@@ -388,6 +393,9 @@ class State:
 
     def apply_gates(self, gl: GateList):
         qs_apply_gates(self.handle, gl)
+
+    def apply_gates_smgp(self, gl: GateList):
+        qs_apply_gates_smgp(self.handle, gl)
 
     def apply_plan(self, plan):
         qs_apply_plan(self.handle, plan)

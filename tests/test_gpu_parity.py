@@ -513,3 +513,41 @@ def test_commute_plans_match_oracle(Q, oracle, dtype, family, k_max, t):
     got, _ = run_plan(Q, c, dtype, psi0, k_max=k_max, tile_qubits=t, low_qubits=4, commute=1)
     assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
     assert 1 - oracle.fidelity(ref, got) <= (1e-6 if dtype == 0 else 1e-12)
+
+
+def _every_qubit_layers(n):
+    """Two layers of U3 on every qubit around a CNOT chain: layers with no
+    free qubit for the segments."""
+    c = qsynth.Circuit(n)
+    for q in range(n):
+        c.add("u3", (q,), (0.3 + q, 0.2, 0.1 * q))
+    for q in range(n - 1):
+        c.add("cx", (q, q + 1))
+    for q in range(n):
+        c.add("h", (q,))
+    return c
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("family,n", [("random", 5), ("random", 9), ("random", 14), ("hea", 12), ("qaoa", 12),
+                                      ("brickwork", 16), ("allq", 11), ("random", 19)])
+def test_smgp_matches_oracle(Q, oracle, dtype, family, n):
+    """Staggered multi-gate launches (DAG layers of one- and controlled
+    one-qubit gates over cyclically assigned state segments) give the
+    oracle's state: random circuits with SWAP and dense two-qubit gates
+    mixed in (those run one sweep each), HEA and QAOA layers, brickwork, and
+    a layer touching every qubit (split into chunks that leave enough qubits
+    for the segments), both precisions."""
+    c = {"random": lambda: qsynth.random_circuit(n, 12 * n, seed=n, max_dense=2),
+         "hea": lambda: qsynth.hea_rxyz(n),
+         "qaoa": lambda: qsynth.qaoa_maxcut(n),
+         "brickwork": lambda: qsynth.brickwork(n, 6, seed=n),
+         "allq": lambda: _every_qubit_layers(n)}[family]()
+    psi0 = qsynth.random_state(n, seed=4)
+    ref = oracle.run(c, psi0.copy())
+    s = Q.State(n, dtype)
+    s.load(psi0)
+    s.apply_gates_smgp(Q.GateList(c))
+    got = s.amplitudes()
+    s.close()
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
