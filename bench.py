@@ -756,7 +756,7 @@ def main():
                      "kernel_gbs": round(pe.bytes[Q.PROF_EXPECT] / (ex_ms * 1e-3) / 1e9, 1) if ex_ms > 0 else None,
                      "state_reads": round(pe.bytes[Q.PROF_EXPECT] / S, 2),
                      "bytes": "one read of the state (S) per group of terms whose X parts above the tile bits "
-                              "span at most 8 dimensions"}
+                              "span at most 9 dimensions"}
 
     # ---- the same circuit with Pauli-rotation contraction (beside the paper's rule) ----
     if a.pauli and a.strategy == Q.STRATEGY_GREEDY:

@@ -248,8 +248,8 @@ qs_status launch_norm_full(qs_state_s &s, double *d_out_slots);
 qs_status ensure_partials(qs_state_s &s, size_t count);
 // kernels_expect.hip: Pauli-sum expectation, one read of the state per group
 // of terms whose high X parts span at most kExpMaxD dimensions
-constexpr int kExpMaxD = 8;            // span dimension of a group (coset = 2^D tiles)
-constexpr int kExpMaxTerms = 8;        // terms per group
+constexpr int kExpMaxD = 9;            // span dimension of a group (coset = 2^D tiles)
+constexpr int kExpMaxTerms = 9;        // terms per group (a random term adds one dimension)
 constexpr int kExpCosetBits64 = 14;    // coset of 2^14 complex64 amplitudes = 128 KiB LDS
 constexpr int kExpCosetBits128 = 13;   // 2^13 complex128 amplitudes = 128 KiB LDS
 constexpr int kExpAmps64 = 16;         // amplitudes one thread stages per coset
