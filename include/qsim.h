@@ -166,9 +166,14 @@ qs_status qs_apply_gates_smgp(qs_state s, const qs_gate *gates, size_t n_gates);
 
 /* -------------------------------------------------- contraction (host) */
 /* Build a plan for an n-qubit circuit: the dependency DAG of Section 3.4
- * (gates sharing a qubit keep program order), blocks merged under the chosen
- * strategy with FP64 block products, and blocks packed into tile passes.
- * Host only.  opts may be NULL (defaults). */
+ * (gates sharing a qubit keep program order; with opts->commute, gates and
+ * blocks that are diagonal on every qubit they share may pass each other, as
+ * may Pauli-rotation blocks whose strings commute), blocks merged under the
+ * chosen strategy with FP64 block products, and blocks packed into tile
+ * passes.  Host only, except the learned strategy, which evaluates the cost
+ * model on the current device.  opts may be NULL (defaults).  The commute
+ * option's greedy rule scans the blocks a gate may join, O(gates x blocks)
+ * in the worst case (many mutually commuting gates). */
 qs_status qs_contract(int n, const qs_gate *gates, size_t n_gates,
                       const qs_contract_opts *opts, qs_plan *out);
 qs_status qs_plan_destroy(qs_plan p);
