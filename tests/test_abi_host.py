@@ -495,3 +495,30 @@ def test_commute_needs_fewer_passes_on_qft(Q):
 def test_commute_flag_validated(Q):
     with pytest.raises(Q.QsimError):
         _plan(Q, qsynth.ghz(6), commute=2)
+
+
+@pytest.mark.parametrize("strategy", ["greedy", "pauli", "none"])
+def test_commute_with_every_strategy_replays_exactly(Q, oracle, strategy):
+    """The commute option combined with the rotation contraction (rotation
+    blocks and diagonal blocks passing each other in the packer) and with
+    one block per gate: the plan still reproduces the circuit exactly."""
+    n = 10
+    parts = [qsynth.ucc(n, n_exp=6, seed=5)[0], qsynth.qaoa_maxcut(n), qsynth.qft(n)]
+    c = qsynth.Circuit(n, [g for p in parts for g in p.gates])
+    st = {"greedy": Q.STRATEGY_GREEDY, "pauli": Q.STRATEGY_PAULI, "none": Q.STRATEGY_NONE}[strategy]
+    plan, _ = _plan(Q, c, k_max=3, tile_qubits=9, low_qubits=1, strategy=st, commute=1)
+    try:
+        info = Q.qs_plan_info_get(plan)
+        qls, mats, mems = [], [], []
+        for b in range(info.n_blocks):
+            qs, U, mem = Q.qs_plan_block(plan, b)
+            qls.append(qs)
+            mats.append(U)
+            mems.append(mem)
+    finally:
+        Q.qs_plan_destroy(plan)
+    assert sorted(g for m in mems for g in m) == list(range(len(c.gates)))
+    psi0 = qsynth.random_state(n, seed=6)
+    ref = oracle.run(c, psi0.copy())
+    got = greedy.apply_blocks(psi0.copy(), n, qls, mats)
+    assert np.max(np.abs(got - ref)) < 1e-12

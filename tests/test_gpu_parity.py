@@ -529,8 +529,9 @@ def _every_qubit_layers(n):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
-@pytest.mark.parametrize("family,n", [("random", 5), ("random", 9), ("random", 14), ("hea", 12), ("qaoa", 12),
-                                      ("brickwork", 16), ("allq", 11), ("random", 19)])
+@pytest.mark.parametrize("family,n", [("random", 1), ("random", 2), ("random", 3), ("random", 5), ("random", 9),
+                                      ("random", 14), ("hea", 12), ("qaoa", 12), ("brickwork", 16), ("allq", 11),
+                                      ("random", 19)])
 def test_smgp_matches_oracle(Q, oracle, dtype, family, n):
     """Staggered multi-gate launches (DAG layers of one- and controlled
     one-qubit gates over cyclically assigned state segments) give the
