@@ -200,7 +200,8 @@ __device__ void run_tiles(typename AmpOf<R>::A *psi, const PassDev &pd, uint64_t
             if ((uint32_t)j < nj) pre[j] = *gptr(nbase, j);
         for (int b = 0; b < pa.nblocks; ++b) {
             if (pd.blocks[pa.block0 + b].kind == BK_SKIP) continue;   // folded into a group (uniform)
-            apply_block<R, WIDE, false, TT, false>(tile, pa.t, pd.blocks + pa.block0 + b, pool, base);
+            apply_block<R, WIDE, false, TT, false>(TilePtr{reinterpret_cast<unsigned char *>(tile)}, pa.t,
+                                                   pd.blocks + pa.block0 + b, pool, base);
             __syncthreads();
         }
         double nacc = 0;

@@ -69,7 +69,7 @@ enum : int32_t {
     BK_PAULI = 4,   // Pauli rotation: y[k] = c psi[k] + d sigma(k^x) psi[k^x]
     BK_PAULIG = 5,  // k consecutive Pauli rotations with independent X parts, one lane per coset
     BK_SKIP = 6,    // folded into the preceding group (no work, no barrier)
-    BK_BDMFMA = 7,  // complex64 permuted block-diagonal, classes of 4 or 8, on MFMA (staged passes)
+    BK_BDMFMA = 7,  // complex64 permuted block-diagonal, classes of 2, 4 or 8, on MFMA (staged passes)
 };
 
 struct BlockDev {

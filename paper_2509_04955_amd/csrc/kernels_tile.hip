@@ -115,7 +115,11 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // complex64 tile runs 3 workgroups per CU, leaving about 20 KB of LDS per
 // workgroup for the operands.  Unstaged 2^13- and 2^14-amplitude complex64
 // tiles run with 512 and 1024 threads (8 vectors per thread, 4 waves per
-// SIMD): 2 workgroups per CU and 1, the same wave count as 2^12 tiles.
+// SIMD): 2 workgroups per CU and 1, the same wave count as 2^12 tiles.  The
+// staged 512-thread variant prefetches 6 of its 8 vectors: 6 leave the
+// compiler three spilled registers, reloaded only in the staged 5- and
+// 6-qubit monomial paths (measured 1.8 % faster per pass than 4 on the
+// 30-qubit UCC circuit); with all 8 the reloads move into the store phase.
 template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
 constexpr int tile_waves() {
     // NJ = 0 (tiles below 2^9 complex64 amplitudes) never fills a CU anyway
@@ -123,11 +127,13 @@ constexpr int tile_waves() {
     return WIDE ? 1 : (sizeof(R) == 4 && NJ > 0 && NJ < 16 ? (CL && NJ == 8 ? 3 : 4) : 2);
 }
 
-// LDS of a tile pass.  Unstaged variants of a fixed tile size hold the tile
-// and the per-wave norm slots in static LDS and take no dynamic LDS.  The
-// others declare no static LDS; their dynamic region is the tile (2^t
-// amplitudes), the norm slots, then the staged block operands.
-constexpr size_t kRedBytes = 128;   // NT / 64 doubles for up to 1024 threads
+// LDS of a tile pass.  Unstaged variants of a fixed tile size hold the tile,
+// the per-wave norm slots and the ticket slots in static LDS and take no
+// dynamic LDS.  The others declare no static LDS; their dynamic region is the
+// tile (2^t amplitudes), the norm slots, the ticket slots, then the staged
+// block operands.  Either way the tile sits at an LDS address aligned to
+// kTileAlign (block code then forms addresses with OR and XOR alone).
+constexpr size_t kRedBytes = 128 + 16;   // NT / 64 doubles for up to 1024 threads, two ticket slots
 
 template <typename R, bool WIDE, int NJ, bool CL, int NT = TT>
 __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_tile_pass(
@@ -137,31 +143,37 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     using A = typename AmpOf<R>::A;
     constexpr bool F32 = sizeof(R) == 4;
     constexpr uint32_t APV = F32 ? 2 : 1;  // amplitudes per 16-byte vector
-    constexpr int PFMAX = NT > TT && CL ? 4 : tile_waves<R, WIDE, NJ, CL, NT>() <= 3 ? (sizeof(R) == 8 ? 8 : 16) : kPrefetch;
+    constexpr int PFMAX = NT > TT && CL ? 6 : tile_waves<R, WIDE, NJ, CL, NT>() <= 3 ? (sizeof(R) == 8 ? 8 : 16) : kPrefetch;
     constexpr int PF = NJ > 0 ? (NJ < PFMAX ? NJ : PFMAX) : kPrefetch;
     constexpr int EX = NJ > PF ? NJ - PF : 0;   // compile-time tiles: vectors loaded after the blocks
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    static_assert(NT / 64 * sizeof(double) <= kRedBytes, "norm slots");
+    static_assert(NT / 64 * sizeof(double) + 2 * sizeof(uint64_t) <= kRedBytes, "norm and ticket slots");
     const int T = pa.t;
     const uint32_t tsize = 1u << T;
     A *tile;
     double *red;
-    R *cst;
+    uint64_t *next_slot;
+    R *cst = nullptr;
     if constexpr (NJ > 0 && !CL) {
-        // fixed tile size, no staged operands: tile and norm slots in static
-        // LDS, whose addresses are constants the compiler folds into every
-        // access (the staged variants keep the dynamic layout: with a static
-        // tile their register allocation spills)
-        __shared__ __align__(16) A tile_s[NJ * NT * APV];
+        // fixed tile size, no staged operands: tile and slots in static LDS,
+        // whose addresses are constants the compiler folds into every access
+        // (the staged variants keep the dynamic layout: with a static tile
+        // their register allocation spills)
+        __shared__ __align__(kTileAlign) A tile_s[NJ * NT * APV];
         __shared__ double red_s[NT / 64];
+        __shared__ uint64_t next_s[2];
         tile = tile_s;
         red = red_s;
-        cst = reinterpret_cast<R *>(smem_raw);
+        next_slot = next_s;
     } else {
+        // no static LDS in these variants: the dynamic region starts at LDS
+        // address 0, which meets the declared alignment
+        extern __shared__ __align__(kTileAlign) unsigned char smem_raw[];
         tile = reinterpret_cast<A *>(smem_raw);
         red = reinterpret_cast<double *>(smem_raw + (size_t)tsize * sizeof(A));
+        next_slot = reinterpret_cast<uint64_t *>(smem_raw + (size_t)tsize * sizeof(A) + 128);
         cst = reinterpret_cast<R *>(smem_raw + (size_t)tsize * sizeof(A) + kRedBytes);
     }
+    const TileAligned tl{lds_addr(tile)};
     const R sc = pa.apply_scale ? (R)(*scale_in) : (R)1;
     const uint32_t my_li = threadIdx.x * APV;
     const bool active = NJ > 0 || my_li < tsize;   // small tiles: fewer vectors than threads
@@ -173,10 +185,8 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     auto gaddr = [&](uint64_t base, uint32_t j) -> V * {
         return reinterpret_cast<V *>(psi + (base | g_t | tile_offset(j * NT * APV, pa)));
     };
-    auto lds_put = [&](uint32_t j, V v) {
-        const uint32_t si = s_t ^ sw(j * NT * APV);
-        *reinterpret_cast<V *>(tile + si) = v * sc;
-    };
+    const uint32_t h_t = tl.grp(s_t * (uint32_t)sizeof(A));   // this thread's first vector
+    auto lds_put = [&](uint32_t j, V v) { *tl.template at<V>(h_t, sw(j * NT * APV) * (uint32_t)sizeof(A)) = v * sc; };
     // Vectors of a generic tile beyond the prefetch depth: loaded in batches
     // through the prefetch registers once those are in LDS.
     auto load_rest = [&](uint64_t base) {
@@ -194,7 +204,6 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     // a ticket past the last tile), so a workgroup that runs faster than its
     // neighbour on the same CU takes more tiles.  Thread 0 draws the ticket
     // after next into an LDS slot; the loop-top barrier publishes it.
-    __shared__ uint64_t next_slot[2];
     if (threadIdx.x == 0) {
         next_slot[0] = atomicAdd(tickets, 1ull) - ticket0;
         // exactly one ticket past the last tile per workgroup
@@ -252,7 +261,7 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
         // ---- blocks ----
         for (int b = 0; b < pa.nblocks; ++b) {
             if (blocks[pa.block0 + b].kind == BK_SKIP) continue;   // folded into a group (uniform)
-            apply_block<R, WIDE, CL, NT>(tile, T, blocks + pa.block0 + b, pool, base, cst, pa.cl_off);
+            apply_block<R, WIDE, CL, NT>(tl, T, blocks + pa.block0 + b, pool, base, cst, pa.cl_off);
             __syncthreads();
         }
         V ex[EX > 0 ? EX : 1];
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
             // instead of a read latency per stored vector
             V vals[NJ];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) vals[j] = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * NT * APV)));
+            for (int j = 0; j < NJ; ++j) vals[j] = *tl.template at<const V>(h_t, sw(j * NT * APV) * (uint32_t)sizeof(A));
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 st_nt(gaddr(base, j), vals[j]);
@@ -279,7 +288,7 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
             }
         } else if (active) {
             for (uint32_t j = 0; j < nj; ++j) {
-                const V v = *reinterpret_cast<const V *>(tile + (s_t ^ sw(j * NT * APV)));
+                const V v = *tl.template at<const V>(h_t, sw(j * NT * APV) * (uint32_t)sizeof(A));
                 st_nt(gaddr(base, j), v);
                 nacc += norm_of(v);
             }
@@ -782,9 +791,6 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
     std::vector<int> dest;
     const int kind = block_kind(blk, t, dt, &dest, lds);
     if (kind == BK_BDMFMA) {
-        // packs of 8 class members (one class of 8 or two of 4), see
-        // bdiag_mfma_block: A of the pack's 16x16 real form as [lane][step],
-        // column offsets (members 0,2,4,6 then 1,3,5,7), row offsets
         int sub = 0;
         std::vector<int> src, dst;
         bdiag_split(blk.U, d.k, sub, src, dst);
@@ -798,6 +804,36 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
             return sw(o) * 2 * (uint32_t)sizeof(R);
         };
         const int DS = 1 << sub;
+        if (sub < 3) {
+            // classes of 2 or 4, see class_mfma_block: source and destination
+            // byte offsets class by class, then the classes' real forms M
+            // (rows and columns ordered (member, re/im)) as [lane][register]:
+            // product n = (class, row tile, step) is register n / 16 of lane
+            // quad n % 16, whose lane i holds row i of the row tile
+            for (int i = 0; i < D; ++i) pool.push_back(pool_entry<R>(off(src[i])));
+            for (int i = 0; i < D; ++i) pool.push_back(pool_entry<R>(off(dst[i])));
+            const int K2 = 2 * DS, RT = K2 / 4, NREG = DS;
+            std::vector<R> am((size_t)64 * NREG, (R)0);
+            for (int c = 0; c < D / DS; ++c)
+                for (int rt = 0; rt < RT; ++rt)
+                    for (int st = 0; st < K2; ++st) {
+                        const int n = (c * RT + rt) * K2 + st, q = n % 16, u = n / 16;
+                        for (int i = 0; i < 4; ++i) {
+                            const int row = 4 * rt + i;
+                            const int r = row / 2, rp = row % 2, cm = st / 2, cp = st % 2;
+                            const cd e = blk.U[(size_t)dst[c * DS + r] * D + src[c * DS + cm]];
+                            const double v = rp == 0 ? (cp == 0 ? e.real() : -e.imag())
+                                                     : (cp == 0 ? e.imag() : e.real());
+                            am[(size_t)(4 * q + i) * NREG + u] = (R)v;
+                        }
+                    }
+            pool.insert(pool.end(), am.begin(), am.end());
+            while (pool.size() % 4) pool.push_back((R)0);  // 16-byte aligned entries
+            return;
+        }
+        // classes of 8: packs of 8 class members, see bdiag_mfma_block: A of
+        // the pack's 16x16 real form as [lane][step], column offsets (members
+        // 0,2,4,6 then 1,3,5,7), row offsets
         for (int p0 = 0; p0 < D; p0 += 8) {
             for (int lane = 0; lane < 64; ++lane)
                 for (int st = 0; st < 4; ++st) {
@@ -849,7 +885,7 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
                 if ((dest[c] >> j) & 1) o |= 1u << d.pos[j];
             pool.push_back((R)u.real());
             pool.push_back((R)u.imag());
-            pool.push_back((R)sw(o));
+            pool.push_back(pool_entry<R>(sw(o) * 2 * (uint32_t)sizeof(R)));   // LDS byte offset
             pool.push_back((R)0);
         }
     } else if (kind == BK_MFMA) {
@@ -896,7 +932,8 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
         const int k = (int)blk.qubits.size(), D = 1 << k;
         const int kind = block_kind(blk, ps.t, dt, nullptr, true);
         size_t e = kind == BK_PAULI   ? 52   // bound: a group record (pivots, 16 offsets, 4 x 8)
-                   : kind == BK_BDMFMA  ? (size_t)(D / 8) * kBdPackFloats
+                   : kind == BK_BDMFMA  ? (bdiag_width(blk) == 8 ? (size_t)(D / 8) * kBdPackFloats
+                                                                  : 2 * (size_t)D + 64 * bdiag_width(blk))
                    : kind == BK_MONO    ? 4 * (size_t)D
                    : kind == BK_MFMA  ? (k == 4 || (k == 5 && !big_staged(ps.t, dt)) ? (size_t)3 * D * D
                                                                                       : (size_t)4 * D * D)
@@ -942,10 +979,10 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     std::vector<int> src, dst;
     if (structured_enabled() && bdiag_gap() > 0 && k >= 3 && bdiag_split(b.U, k, sub, src, dst) &&
         bdiag_supported(k, sub, dt)) {
-        // complex64 4-qubit blocks with classes of 8 in staged passes: 16x16 real
-        // products on MFMA (32 multiply-adds per amplitude on the vector ALU;
-        // classes of 4 measured slower there, the MFMA doing twice their work)
-        if (lds && dt == QS_C64 && mfma_enabled() && bdmfma_enabled() && t - k >= 4 && k == 4 && sub == 3)
+        // complex64 4-qubit blocks in staged passes: classes of 8 as 16x16 real
+        // products (32 multiply-adds per amplitude on the vector ALU), classes
+        // of 2 and 4 as the 16-block 4x4 product (8 and 16 there) on MFMA
+        if (lds && dt == QS_C64 && mfma_enabled() && bdmfma_enabled() && t - k >= 4 && k == 4 && sub >= 1)
             return BK_BDMFMA;
         return BK_BDIAG;
     }
@@ -969,7 +1006,10 @@ int bdiag_log_width(const HBlock &b) {
 
 bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt) {
     // stage the pass's operands in LDS when they fit and the pass has blocks
-    // that read per-lane operands (MFMA, wide monomial)
+    // that read per-lane operands (MFMA, classes of 8 on MFMA, wide monomial).
+    // Classes of 2 and 4 go to the matrix cores only in passes staged for
+    // those: on their own they run faster in the unstaged variant, whose
+    // prefetch covers the whole next tile.
     if (!staged_enabled()) return false;
     const size_t budget = lds_operand_budget(ps.t, dt);
     if (!budget) return false;
@@ -977,7 +1017,7 @@ bool pass_staged(const std::vector<HBlock> &blocks, const HPass &ps, qs_dtype dt
     for (int64_t b = ps.block0; b < ps.block0 + ps.nblocks; ++b) {
         const int k = (int)blocks[b].qubits.size();
         const int kind = block_kind(blocks[b], ps.t, dt, nullptr, true);
-        per_lane |= kind == BK_MFMA || kind == BK_BDMFMA || (kind == BK_MONO && k >= 4);
+        per_lane |= kind == BK_MFMA || (kind == BK_BDMFMA && bdiag_width(blocks[b]) == 8) || (kind == BK_MONO && k >= 4);
         dense_wide |= kind == BK_DENSE && k > 3;
     }
     return per_lane && !dense_wide && pass_operand_bytes(blocks, ps, dt) <= budget;

@@ -96,17 +96,73 @@ struct Mfma<double> {
 // swizzle their base once and XOR in wave-uniform swizzled offsets.
 __host__ __device__ __forceinline__ uint32_t sw(uint32_t li) { return li ^ (((li >> 4) & 7u) << 1); }
 
+// ---- tile references ---------------------------------------------------------
+// Block code names an LDS amplitude by a group handle and an in-group byte
+// offset: grp(g) for a group whose swizzled byte offset in the tile is g, and
+// at<T>(h, o) for the element at byte g ^ o (g and o on disjoint bits, so this
+// is g + o).  TileAligned is a tile at an LDS address aligned to kTileAlign,
+// above every tile size: base + (g ^ o) = (base | g) ^ o, so a group costs one
+// OR and an access one XOR (an LDS base that is only known at link time,
+// as a dynamic region's, would otherwise cost an add per access).  TilePtr
+// places a tile at any address.
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+constexpr uint32_t kTileAlign = 1u << 17;
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(const lds_u8 *)p; }
+
+struct TileAligned {
+    uint32_t base;   // LDS address, a multiple of kTileAlign
+    __device__ __forceinline__ uint32_t grp(uint32_t g) const { return base | g; }
+    template <typename T>
+    __device__ __forceinline__ T *at(uint32_t h, uint32_t o) const {
+        return (T *)(lds_u8 *)(uintptr_t)(h ^ o);
+    }
+};
+
+struct TilePtr {
+    unsigned char *base;
+    __device__ __forceinline__ uint32_t grp(uint32_t g) const { return g; }
+    template <typename T>
+    __device__ __forceinline__ T *at(uint32_t h, uint32_t o) const {
+        return reinterpret_cast<T *>(base + (h ^ o));
+    }
+};
+
+// Matrix-core blocks walk a block's groups in chunks of 16 (column jc of
+// chunk ch is group 16 ch + jc).  Inserting the block's zero bits is linear
+// over disjoint bit fields and so is the swizzle, so a group's handle is the
+// lane's part, grp(sw(dep(jc)) * bytes) formed once per block, XOR the
+// chunk's part sw(dep(16 ch)) * bytes, which is uniform over the wave and
+// formed on the scalar unit.
+template <int K>
+__device__ __forceinline__ uint32_t chunk_part(uint32_t ch, const int *pos, uint32_t bytes) {
+    uint32_t c = ch * 16;
+#pragma unroll
+    for (int j = 0; j < K; ++j) c = ins0_32(c, pos[j]);
+    return sw(c) * bytes;
+}
+template <int K, typename TL>
+__device__ __forceinline__ uint32_t lane_part(const TL &tl, uint32_t jc, const int *pos, uint32_t bytes) {
+    uint32_t c = jc;
+#pragma unroll
+    for (int j = 0; j < K; ++j) c = ins0_32(c, pos[j]);
+    return tl.grp(sw(c) * bytes);
+}
+
+// A 32-bit pattern stored in an operand pool entry (bit-cast, not converted).
+__device__ __forceinline__ uint32_t pool_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t pool_bits(double v) { return (uint32_t)__double_as_longlong(v); }
+
 // ---- vector-ALU block: one group of 2^K amplitudes per lane -------------
 // Two groups per iteration when K <= 3 so each lane has independent LDS
 // loads in flight.
-template <int K, typename R>
-__device__ __forceinline__ void dense_group(typename AmpOf<R>::A *tile, uint32_t b, const uint32_t *off,
-                                            const R *__restrict__ U) {
+template <int K, typename R, typename TL>
+__device__ __forceinline__ void dense_group(TL tl, uint32_t h, const uint32_t *off, const R *__restrict__ U) {
     using A = typename AmpOf<R>::A;
     constexpr int D = 1 << K;
     A v[D];
 #pragma unroll
-    for (int r = 0; r < D; ++r) v[r] = tile[b ^ off[r]];
+    for (int r = 0; r < D; ++r) v[r] = *tl.template at<A>(h, off[r]);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
         R yr = 0, yi = 0;
@@ -121,13 +177,12 @@ __device__ __forceinline__ void dense_group(typename AmpOf<R>::A *tile, uint32_t
         A y;
         y.x = yr;
         y.y = yi;
-        tile[b ^ off[r]] = y;
+        *tl.template at<A>(h, off[r]) = y;
     }
 }
 
-template <int K, typename R, int NT = TT>
-__device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                           const R *__restrict__ U) {
+template <int K, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void valu_block(TL tl, int T, const BlockDev *bd, const R *__restrict__ U) {
     using A = typename AmpOf<R>::A;
     constexpr int D = 1 << K;
     int pos[K];
@@ -140,14 +195,14 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if ((r >> j) & 1) o |= 1u << pos[j];
-        off[r] = sw(o);
+        off[r] = sw(o) * (uint32_t)sizeof(A);
     }
     const uint32_t G = 1u << (T - K);
     auto base_of = [&](uint32_t g) {
         uint32_t b = g;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-        return sw(b);
+        return tl.grp(sw(b) * (uint32_t)sizeof(A));
     };
     if constexpr (K <= 3) {
         if (G >= 2 * NT) {
@@ -160,8 +215,8 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
                 A v0[D], v1[D];
 #pragma unroll
                 for (int r = 0; r < D; ++r) {
-                    v0[r] = tile[b0 ^ off[r]];
-                    v1[r] = tile[b1 ^ off[r]];
+                    v0[r] = *tl.template at<A>(b0, off[r]);
+                    v1[r] = *tl.template at<A>(b1, off[r]);
                 }
 #pragma unroll
                 for (int r = 0; r < D; ++r) {
@@ -183,8 +238,8 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
                     y0.y = y0i;
                     y1.x = y1r;
                     y1.y = y1i;
-                    tile[b0 ^ off[r]] = y0;
-                    tile[b1 ^ off[r]] = y1;
+                    *tl.template at<A>(b0, off[r]) = y0;
+                    *tl.template at<A>(b1, off[r]) = y1;
                 }
             }
             return;
@@ -192,20 +247,20 @@ __device__ __forceinline__ void valu_block(typename AmpOf<R>::A *tile, int T, co
     }
     for (uint32_t g = threadIdx.x; g < G; g += NT) {
         asm volatile("" ::: "memory");
-        dense_group<K, R>(tile, base_of(g), off, U);
+        dense_group<K, R>(tl, base_of(g), off, U);
     }
 }
 
 // ---- monomial block: one nonzero per column ---------------------------------
 // y[dest(c)] = u_c x[c].  Diagonal blocks are the case dest(c) = c.  Pool entry
-// c is a 4-value record (Re u_c, Im u_c, swizzled tile offset of dest(c), 0),
+// c is a 4-value record (Re u_c, Im u_c, swizzled tile byte offset of dest(c)
+// as a bit pattern, 0),
 // read as wave-uniform scalars when a group fits one lane.  A group of 2^K amplitudes is handled by LPG lanes of
 // one wave (LPG = 1 for K <= 3, 2^(K-3) above), each holding 8 or fewer
 // sources; the lanes of a wave issue all their LDS reads before any write, so
 // the in-place permutation is safe.
-template <int K, typename R, int NT = TT>
-__device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                           const R *__restrict__ E) {
+template <int K, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void mono_block(TL tl, int T, const BlockDev *bd, const R *__restrict__ E) {
     using A = typename AmpOf<R>::A;
     constexpr int LPG = K <= 3 ? 1 : (1 << (K > 3 ? K - 3 : 0));
     constexpr int SPL = (1 << K) / LPG;
@@ -227,21 +282,21 @@ __device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, co
         uint32_t b = g;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-        const uint32_t sb = sw(b) ^ sw(deposit(p << KL));
+        const uint32_t hs = tl.grp((sw(b) ^ sw(deposit(p << KL))) * (uint32_t)sizeof(A));
         A v[SPL];
 #pragma unroll
-        for (int i = 0; i < SPL; ++i) v[i] = tile[sb ^ sw(deposit((uint32_t)i))];
-        const uint32_t sbase = sw(b);
+        for (int i = 0; i < SPL; ++i) v[i] = *tl.template at<A>(hs, sw(deposit((uint32_t)i)) * (uint32_t)sizeof(A));
+        const uint32_t hd = tl.grp(sw(b) * (uint32_t)sizeof(A));
         // entry c = p * SPL + i: wave-uniform (scalar loads) when LPG == 1
         const R *Ep = E + 4 * (p * SPL);
 #pragma unroll
         for (int i = 0; i < SPL; ++i) {
             const R ur = Ep[4 * i], ui = Ep[4 * i + 1];
-            const uint32_t dst = (uint32_t)Ep[4 * i + 2];
+            const uint32_t dst = pool_bits(Ep[4 * i + 2]);
             A y;
             y.x = ur * v[i].x - ui * v[i].y;
             y.y = ur * v[i].y + ui * v[i].x;
-            tile[sbase ^ dst] = y;
+            *tl.template at<A>(hd, dst) = y;
         }
     };
     if constexpr (K <= 3) {
@@ -256,9 +311,6 @@ __device__ __forceinline__ void mono_block(typename AmpOf<R>::A *tile, int T, co
     for (uint32_t tk = threadIdx.x; tk < tasks; tk += NT) group(tk);
 }
 
-// A 32-bit pattern stored in an operand pool entry (bit-cast, not converted).
-__device__ __forceinline__ uint32_t pool_bits(float v) { return __float_as_uint(v); }
-__device__ __forceinline__ uint32_t pool_bits(double v) { return (uint32_t)__double_as_longlong(v); }
 
 // ---- permuted block-diagonal block ------------------------------------------
 // The block's 2^K rows and columns split into 2^(K-S) classes of 2^S that U
@@ -268,26 +320,23 @@ __device__ __forceinline__ uint32_t pool_bits(double v) { return (uint32_t)__dou
 // whole group, so the in-place update only touches its own amplitudes, and
 // every operand is wave-uniform (scalar loads).  The offsets are byte offsets
 // stored as bit patterns: one XOR per LDS address.
-template <int K, int S, typename R, int NT = TT>
-__device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                            const R *__restrict__ E) {
+template <int K, int S, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void bdiag_block(TL tl, int T, const BlockDev *bd, const R *__restrict__ E) {
     using A = typename AmpOf<R>::A;
     constexpr int D = 1 << K, DS = 1 << S, NC = D / DS;
     int pos[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
     const R *B = E + 2 * D;
-    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
-    auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
     const uint32_t G = 1u << (T - K);
     for (uint32_t g = threadIdx.x; g < G; g += NT) {
         uint32_t b = g;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-        const uint32_t sb = sw(b) * (uint32_t)sizeof(A);
+        const uint32_t h = tl.grp(sw(b) * (uint32_t)sizeof(A));
         A v[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) v[i] = at(sb ^ pool_bits(E[i]));
+        for (int i = 0; i < D; ++i) v[i] = *tl.template at<A>(h, pool_bits(E[i]));
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             // keeps each class's operand loads beside their use (hoisted out of
@@ -309,7 +358,7 @@ __device__ __forceinline__ void bdiag_block(typename AmpOf<R>::A *tile, int T, c
                 A y;
                 y.x = yr;
                 y.y = yi;
-                at(sb ^ pool_bits(E[D + j * DS + r])) = y;
+                *tl.template at<A>(h, pool_bits(E[D + j * DS + r])) = y;
             }
         }
     }
@@ -353,16 +402,13 @@ __device__ __forceinline__ void rot_pair(A &y0, A &y1, const A a, const A b, uin
 // outside the tile (their parity is fixed per tile: gbase, the global index of
 // tile position 0, carries them), c, d.  One lane per pair (k, k ^ x), or per
 // amplitude when x = 0 (diagonal).
-template <typename R, int NT, int MODE>
-__device__ __forceinline__ void pauli_block_m(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
-                                              uint64_t gbase) {
+template <typename R, int NT, int MODE, typename TL>
+__device__ __forceinline__ void pauli_block_m(TL tl, int T, const R *__restrict__ E, uint64_t gbase) {
     using A = typename AmpOf<R>::A;
     const uint32_t x = pool_bits(E[0]), zt = pool_bits(E[1]);
     const uint64_t zo = (uint64_t)pool_bits(E[2]) | ((uint64_t)pool_bits(E[3]) << 32);
     const uint32_t so = (uint32_t)__builtin_popcountll(gbase & zo) & 1u;
     const R cr = E[4], ci = E[5], dr = E[6], di = E[7];
-    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
-    auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
     // sign of sigma(j) as a float sign bit: ((|j & zt| + so) & 1) << 31
     auto sbit = [&](uint32_t j) { return (((uint32_t)__builtin_popcount(j & zt) ^ so) & 1u) << 31; };
     if (x == 0) {
@@ -370,12 +416,12 @@ __device__ __forceinline__ void pauli_block_m(typename AmpOf<R>::A *tile, int T,
         for (uint32_t k = threadIdx.x; k < (1u << T); k += NT) {
             const bool neg = sbit(k) != 0;
             const R fr = neg ? mr : pr, fi = neg ? mi : pi;
-            A &v = at(sw(k) * (uint32_t)sizeof(A));
-            const A a = v;
+            A *v = tl.template at<A>(tl.grp(sw(k) * (uint32_t)sizeof(A)), 0u);
+            const A a = *v;
             A y;
             y.x = fr * a.x - fi * a.y;
             y.y = fr * a.y + fi * a.x;
-            v = y;
+            *v = y;
         }
         return;
     }
@@ -388,13 +434,14 @@ __device__ __forceinline__ void pauli_block_m(typename AmpOf<R>::A *tile, int T,
     const uint32_t half = 1u << (T - 1);
     auto pair = [&](uint32_t g) {
         const uint32_t k0 = ins0_32(g, h);
-        const uint32_t o0 = sw(k0) * (uint32_t)sizeof(A), o1 = o0 ^ swx;
-        const A a = at(o0), b = at(o1);
+        const uint32_t h0 = tl.grp(sw(k0) * (uint32_t)sizeof(A));
+        A *p0 = tl.template at<A>(h0, 0u), *p1 = tl.template at<A>(h0, swx);
+        const A a = *p0, b = *p1;
         const uint32_t s0 = sbit(k0), s1 = s0 ^ sx;
         A y0, y1;
         rot_pair<MODE>(y0, y1, a, b, s0, s1, cr, ci, dr, di);
-        at(o0) = y0;
-        at(o1) = y1;
+        *p0 = y0;
+        *p1 = y1;
     };
     if (half >= 2 * NT) {
         // every lane has exactly half / (2 NT) pairs of pairs: two independent
@@ -409,12 +456,11 @@ __device__ __forceinline__ void pauli_block_m(typename AmpOf<R>::A *tile, int T,
 }
 
 // mode (BlockDev.sub): coefficient form, see rot_pair
-template <typename R, int NT = TT>
-__device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
-                                            uint64_t gbase, int mode) {
-    if (mode == 1) pauli_block_m<R, NT, 1>(tile, T, E, gbase);
-    else if (mode == 2) pauli_block_m<R, NT, 2>(tile, T, E, gbase);
-    else pauli_block_m<R, NT, 0>(tile, T, E, gbase);
+template <typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void pauli_block(TL tl, int T, const R *__restrict__ E, uint64_t gbase, int mode) {
+    if (mode == 1) pauli_block_m<R, NT, 1>(tl, T, E, gbase);
+    else if (mode == 2) pauli_block_m<R, NT, 2>(tl, T, E, gbase);
+    else pauli_block_m<R, NT, 0>(tl, T, E, gbase);
 }
 
 // ---- group of M Pauli rotations (M = 2, 3) -------------------------------------
@@ -427,13 +473,10 @@ __device__ __forceinline__ void pauli_block(typename AmpOf<R>::A *tile, int T, c
 // forms (2 bits each, see rot_pair), swizzled byte offsets of the 2^M members
 // (16 entries), then per rotation: z over tile positions, z of the qubits
 // outside the tile (two entries), the parities |x_j & z| as a mask over j, c, d.
-template <typename R, int M, int NT = TT>
-__device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, const R *__restrict__ E,
-                                            uint64_t gbase) {
+template <typename R, int M, int NT = TT, typename TL>
+__device__ __forceinline__ void pauli_group(TL tl, int T, const R *__restrict__ E, uint64_t gbase) {
     using A = typename AmpOf<R>::A;
     constexpr int NM = 1 << M;
-    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
-    auto at = [&](uint32_t byte) -> A & { return *reinterpret_cast<A *>(tb + byte); };
     int piv[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) piv[j] = (int)pool_bits(E[j]);
@@ -444,10 +487,10 @@ __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, c
         uint32_t k0 = g;
 #pragma unroll
         for (int j = 0; j < M; ++j) k0 = ins0_32(k0, piv[j]);
-        const uint32_t base = sw(k0) * (uint32_t)sizeof(A);
+        const uint32_t hb = tl.grp(sw(k0) * (uint32_t)sizeof(A));
         A v[NM];
 #pragma unroll
-        for (int c = 0; c < NM; ++c) v[c] = at(base ^ pool_bits(E[4 + c]));
+        for (int c = 0; c < NM; ++c) v[c] = *tl.template at<A>(hb, pool_bits(E[4 + c]));
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const R *Ri = Rt + 8 * i;
@@ -476,7 +519,7 @@ __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, c
             else rot(std::integral_constant<int, 0>());
         }
 #pragma unroll
-        for (int c = 0; c < NM; ++c) at(base ^ pool_bits(E[4 + c])) = v[c];
+        for (int c = 0; c < NM; ++c) *tl.template at<A>(hb, pool_bits(E[4 + c])) = v[c];
     }
 }
 
@@ -496,9 +539,8 @@ __device__ __forceinline__ void pauli_group(typename AmpOf<R>::A *tile, int T, c
 // for its tile prefetch at the first of them, which is why complex128 blocks
 // and K = 6 take this path only in the wide variant (whose prefetch is short
 // and whose other blocks are on the vector ALU anyway).
-template <int K, typename R, int NT = TT>
-__device__ __forceinline__ void mfma_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
-                                           const R *__restrict__ Asw) {
+template <int K, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void mfma_block(TL tl, int T, const BlockDev *bd, const R *__restrict__ Asw) {
     using A = typename AmpOf<R>::A;
     using V4 = typename Mfma<R>::V4;
     constexpr int D = 1 << K;
@@ -532,19 +574,19 @@ __device__ __forceinline__ void mfma_block(typename AmpOf<R>::A *tile, int T, co
         for (int s = 0; s < S; ++s) a[i][s] = Asw[((mt0 + i) * S + s) * 64 + lane];
     uint32_t offB[NB];
 #pragma unroll
-    for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq));
-    // float index of output (i, q) relative to 2 * (chunk column base):
-    // 2 * sw(row offset) | part (0: real rows, 1: imaginary rows)
+    for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq)) * (uint32_t)sizeof(A);
+    // byte offset of output (i, q) from the chunk column's amplitude:
+    // sw(row offset) amplitudes, plus one real for the imaginary rows
     uint32_t oc[MPW][4];
 #pragma unroll
     for (int i = 0; i < MPW; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = 16 * (mt0 + i) + Mfma<R>::row(gq, q);
-            oc[i][q] = (2u * sw(deposit(row % D))) | (uint32_t)(row / D);
+            oc[i][q] = ((2u * sw(deposit(row % D))) | (uint32_t)(row / D)) * (uint32_t)sizeof(R);
         }
-    R *tf = reinterpret_cast<R *>(tile);
     const uint32_t nchunks = (1u << (T - K)) / 16;
+    const uint32_t hj = lane_part<K>(tl, (uint32_t)jc, pos, (uint32_t)sizeof(A));
     for (uint32_t r0 = 0; r0 < nchunks; r0 += CR * CPW) {
         V4 acc[CR][MPW];
         uint32_t cbs[CR];
@@ -558,13 +600,10 @@ __device__ __forceinline__ void mfma_block(typename AmpOf<R>::A *tile, int T, co
 #pragma unroll
                 for (int m = 0; m < MPW; ++m) acc[i][m] = V4{0, 0, 0, 0};
                 const uint32_t ch = r0 + wsub + CPW * i;
-                uint32_t cb = (ch < nchunks ? ch : 0) * 16 + jc;
-#pragma unroll
-                for (int j = 0; j < K; ++j) cb = ins0_32(cb, pos[j]);
-                cb = sw(cb);
+                const uint32_t cb = hj ^ chunk_part<K>(ch < nchunks ? ch : 0, pos, (uint32_t)sizeof(A));
                 cbs[i] = cb;
 #pragma unroll
-                for (int m = 0; m < NB; ++m) bv[h][m] = tile[cb ^ offB[m]];
+                for (int m = 0; m < NB; ++m) bv[h][m] = *tl.template at<A>(cb, offB[m]);
             }
 #pragma unroll
             for (int s = 0; s < S; ++s)
@@ -583,7 +622,7 @@ __device__ __forceinline__ void mfma_block(typename AmpOf<R>::A *tile, int T, co
 #pragma unroll
                 for (int m = 0; m < MPW; ++m)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) tf[(2u * cbs[i]) ^ oc[m][q]] = acc[i][m][q];
+                    for (int q = 0; q < 4; ++q) *tl.template at<R>(cbs[i], oc[m][q]) = acc[i][m][q];
             }
         }
         __syncthreads();
@@ -600,8 +639,8 @@ __device__ __forceinline__ void mfma_block(typename AmpOf<R>::A *tile, int T, co
 // amplitude R mod 2^K, real part when R < 2^K (K = 3 has one M-tile holding
 // both parts); for FP64 the row of item q is 16 m + lane/16 + 4q.  CPI chunks are in flight per wave (CPI * MT accumulator
 // chains).
-template <int K, typename R, int NT = TT>
-__device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T, const BlockDev *bd, const R *As) {
+template <int K, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void mfma_block_lds(TL tl, int T, const BlockDev *bd, const R *As) {
     using A = typename AmpOf<R>::A;
     using V4 = typename Mfma<R>::V4;
     constexpr int D = 1 << K;
@@ -624,32 +663,29 @@ __device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T
     };
     uint32_t offB[NB];
 #pragma unroll
-    for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq));
-    // float index of output (m, q) relative to 2 * (chunk column base):
-    // 2 * sw(row offset) | part
+    for (int m = 0; m < NB; ++m) offB[m] = sw(deposit(4 * m + gq)) * (uint32_t)sizeof(A);
+    // byte offset of output (m, q) from the chunk column's amplitude:
+    // sw(row offset) amplitudes, plus one real for the imaginary rows
     uint32_t oc[MT][4];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = 16 * m + Mfma<R>::row(gq, q);
-            oc[m][q] = (2u * sw(deposit(row % D))) | (uint32_t)(row / D);
+            oc[m][q] = ((2u * sw(deposit(row % D))) | (uint32_t)(row / D)) * (uint32_t)sizeof(R);
         }
-    R *tf = reinterpret_cast<R *>(tile);
     const V4 *A4 = reinterpret_cast<const V4 *>(As);
     const uint32_t nchunks = (1u << (T - K)) / 16;
+    const uint32_t hj = lane_part<K>(tl, (uint32_t)jc, pos, (uint32_t)sizeof(A));
     for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += (NT / 64) * CPI) {
         uint32_t cb[CPI];
         A bv[CPI][NB];
 #pragma unroll
         for (int h = 0; h < CPI; ++h) {
             const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
-            uint32_t c = ch * 16 + jc;
+            cb[h] = hj ^ chunk_part<K>(ch, pos, (uint32_t)sizeof(A));
 #pragma unroll
-            for (int j = 0; j < K; ++j) c = ins0_32(c, pos[j]);
-            cb[h] = sw(c);
-#pragma unroll
-            for (int m = 0; m < NB; ++m) bv[h][m] = tile[cb[h] ^ offB[m]];
+            for (int m = 0; m < NB; ++m) bv[h][m] = *tl.template at<A>(cb[h], offB[m]);
         }
         V4 acc[CPI][MT];
 #pragma unroll
@@ -677,7 +713,7 @@ __device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) tf[(2u * cb[h]) ^ oc[m][q]] = acc[h][m][q];
+                    for (int q = 0; q < 4; ++q) *tl.template at<R>(cb[h], oc[m][q]) = acc[h][m][q];
             }
         }
     }
@@ -695,8 +731,8 @@ __device__ __forceinline__ void mfma_block_lds(typename AmpOf<R>::A *tile, int T
 // in LDS: [g = Ur, Ui, Ur+Ui][M-tile][s/4][lane][s%4].  As in mfma_block_lds
 // each wave owns whole chunks: no barrier inside the block.  K = 4 keeps all
 // of A in registers for the block; K = 5 re-reads it per chunk.
-template <int K, typename R, int NT = TT>
-__device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int T, const BlockDev *bd, const R *As) {
+template <int K, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void mfma3m_block_lds(TL tl, int T, const BlockDev *bd, const R *As) {
     using A = typename AmpOf<R>::A;
     using V4 = typename Mfma<R>::V4;
     static_assert(K == 4 || K == 5, "three-product GEMM needs 2^K >= 16");
@@ -721,12 +757,12 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
     };
     uint32_t offB[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) offB[s] = sw(deposit(4 * s + gq));
+    for (int s = 0; s < S; ++s) offB[s] = sw(deposit(4 * s + gq)) * (uint32_t)sizeof(A);
     uint32_t oc[MT][4];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) oc[m][q] = sw(deposit(16 * m + Mfma<R>::row(gq, q)));
+        for (int q = 0; q < 4; ++q) oc[m][q] = sw(deposit(16 * m + Mfma<R>::row(gq, q))) * (uint32_t)sizeof(A);
     const V4 *A4 = reinterpret_cast<const V4 *>(As);
     auto aidx = [&](int g, int m, int s4) { return ((g * MT + m) * S4 + s4) * 64 + lane; };
     V4 ah[HOIST ? 3 * MT * S4 : 1];
@@ -739,18 +775,16 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
                 for (int s4 = 0; s4 < S4; ++s4) ah[(g * MT + m) * S4 + s4] = A4[aidx(g, m, s4)];
     }
     const uint32_t nchunks = (1u << (T - K)) / 16;
+    const uint32_t hj = lane_part<K>(tl, (uint32_t)jc, pos, (uint32_t)sizeof(A));
     for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += (NT / 64) * CPI) {
         uint32_t cb[CPI];
         A bv[CPI][S];
 #pragma unroll
         for (int h = 0; h < CPI; ++h) {
             const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
-            uint32_t c = ch * 16 + jc;
+            cb[h] = hj ^ chunk_part<K>(ch, pos, (uint32_t)sizeof(A));
 #pragma unroll
-            for (int j = 0; j < K; ++j) c = ins0_32(c, pos[j]);
-            cb[h] = sw(c);
-#pragma unroll
-            for (int s = 0; s < S; ++s) bv[h][s] = tile[cb[h] ^ offB[s]];
+            for (int s = 0; s < S; ++s) bv[h][s] = *tl.template at<A>(cb[h], offB[s]);
         }
         V4 acc[CPI][3][MT];
 #pragma unroll
@@ -791,7 +825,7 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
                         A y;
                         y.x = t1 - t2;
                         y.y = t3 - t1 - t2;
-                        tile[cb[h] ^ oc[m][q]] = y;
+                        *tl.template at<A>(cb[h], oc[m][q]) = y;
                     }
             }
         }
@@ -814,8 +848,8 @@ __device__ __forceinline__ void mfma3m_block_lds(typename AmpOf<R>::A *tile, int
 // may be another pack's columns), so the block needs no barrier.
 constexpr int kBdPackFloats = 256 + 8 + 8;
 
-template <int K, int NT = TT>
-__device__ __forceinline__ void bdiag_mfma_block(float2 *tile, int T, const BlockDev *bd, const float *Es) {
+template <int K, int NT = TT, typename TL>
+__device__ __forceinline__ void bdiag_mfma_block(TL tl, int T, const BlockDev *bd, const float *Es) {
     constexpr int NPK = (1 << K) / 8;
     constexpr int CPI = 2;   // chunks in flight per wave
     const int lane = threadIdx.x & 63;
@@ -839,22 +873,19 @@ __device__ __forceinline__ void bdiag_mfma_block(float2 *tile, int T, const Bloc
         oo[p][0] = ob[0];
         oo[p][1] = ob[1];
     }
-    unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
     const uint32_t nchunks = (1u << (T - K)) / 16;
+    const uint32_t hj = lane_part<K>(tl, (uint32_t)jc, pos, (uint32_t)sizeof(float2));
     for (uint32_t ch0 = (uint32_t)wave * CPI; ch0 < nchunks; ch0 += (NT / 64) * CPI) {
         uint32_t sb[CPI];
         float x[CPI][NPK][4];
 #pragma unroll
         for (int h = 0; h < CPI; ++h) {
             const uint32_t ch = ch0 + h < nchunks ? ch0 + h : ch0;   // a short last round re-reads a valid chunk
-            uint32_t b = ch * 16 + jc;
-#pragma unroll
-            for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
-            sb[h] = sw(b) * (uint32_t)sizeof(float2);
+            sb[h] = hj ^ chunk_part<K>(ch, pos, (uint32_t)sizeof(float2));
 #pragma unroll
             for (int p = 0; p < NPK; ++p)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) x[h][p][s] = *reinterpret_cast<const float *>(tb + (sb[h] ^ io[p][s]));
+                for (int s = 0; s < 4; ++s) x[h][p][s] = *tl.template at<const float>(sb[h], io[p][s]);
         }
         floatx4 acc[CPI][NPK];
 #pragma unroll
@@ -871,10 +902,87 @@ __device__ __forceinline__ void bdiag_mfma_block(float2 *tile, int T, const Bloc
             if (ch0 + h < nchunks) {
 #pragma unroll
                 for (int p = 0; p < NPK; ++p) {
-                    *reinterpret_cast<float2 *>(tb + (sb[h] ^ oo[p][0])) = make_float2(acc[h][p][0], acc[h][p][1]);
-                    *reinterpret_cast<float2 *>(tb + (sb[h] ^ oo[p][1])) = make_float2(acc[h][p][2], acc[h][p][3]);
+                    *tl.template at<float2>(sb[h], oo[p][0]) = make_float2(acc[h][p][0], acc[h][p][1]);
+                    *tl.template at<float2>(sb[h], oo[p][1]) = make_float2(acc[h][p][2], acc[h][p][3]);
                 }
             }
+        }
+    }
+}
+
+// ---- permuted block-diagonal block, classes of 2 or 4, on MFMA (complex64, staged)
+// 4x4x1 MFMA whose A operand comes from lane quad Q of the wave for all 16
+// blocks (broadcast control 4, block Q); Q must be a constant.
+template <int Q = 0>
+__device__ __forceinline__ floatx4 mfma4x4_bcast(int q, float a, float b, floatx4 c) {
+    if constexpr (Q == 15) return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 15, 0);
+    else return q == Q ? __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, Q, 0) : mfma4x4_bcast<Q + 1>(q, a, b, c);
+}
+
+// Classes of 2^S members (S = 1, 2) of a 4-qubit block on the 16-block
+// v_mfma_f32_4x4x1f32: each of its 16 blocks (4 lanes each) forms a 4x4 outer
+// product, and lane 4b + j supplies column j of block b (B operand) and holds
+// that column of the result.  One lane keeps one group of 16 amplitudes in
+// registers, as the vector-ALU class path does, and lane 4b + j's result is
+// its own group's.  Class c's real form M_c (2^(S+1) square, rows and
+// columns ordered (member, re/im)) is the same for every group, so all 16
+// blocks take the A operand (rows 4 r + i, i = 0..3, of row tile r at step
+// st) from one lane quad by the MFMA's broadcast control: product
+// n = (c * RT + r) * 2^(S+1) + st reads register n / 16 of quad n % 16.  The
+// whole of M then sits in 2^S registers per lane, read from LDS once per
+// block.  Output register q of row tile r is part q % 2 of member 2 r + q / 2.
+// Record: 2^K source and 2^K destination byte offsets (bit patterns, read as
+// wave-uniform scalars from the pool), then M as [lane][register] (the
+// staged copy in LDS).  The group's reads all precede its writes and no
+// other lane touches the group, so the block needs no barrier of its own.
+template <int S, int NT = TT, typename TL>
+__device__ __forceinline__ void class_mfma_block(TL tl, int T, const BlockDev *bd, const float *__restrict__ E,
+                                                 const float *Es) {
+    constexpr int K = 4, D = 1 << K, DS = 1 << S, NC = D / DS, K2 = 2 * DS, RT = K2 / 4;
+    constexpr int CG = RT == 1 ? 2 : 1;   // classes per round: two accumulator chains either way
+    static_assert(S == 1 || S == 2, "classes of 2 or 4");
+    using AV = typename std::conditional<S == 2, floatx4, float __attribute__((ext_vector_type(2)))>::type;
+    static_assert(NC * RT * K2 == 16 * DS, "one register per quad and product");
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    const AV am = reinterpret_cast<const AV *>(Es + 2 * D)[threadIdx.x & 63];   // every lane, before the group loop
+    const uint32_t G = 1u << (T - K);
+    for (uint32_t g = threadIdx.x; g < G; g += NT) {
+        uint32_t b = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
+        const uint32_t h = tl.grp(sw(b) * (uint32_t)sizeof(float2));
+        float2 v[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[i] = *tl.template at<float2>(h, pool_bits(E[i]));
+#pragma unroll
+        for (int c0 = 0; c0 < NC; c0 += CG) {
+            floatx4 acc[CG][RT];
+#pragma unroll
+            for (int e = 0; e < CG; ++e)
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[e][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < K2; ++st)
+#pragma unroll
+                for (int e = 0; e < CG; ++e) {
+                    const float2 &xm = v[(c0 + e) * DS + st / 2];
+                    const float x = st & 1 ? xm.y : xm.x;
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) {
+                        const int n = ((c0 + e) * RT + r) * K2 + st;
+                        acc[e][r] = mfma4x4_bcast(n % 16, am[n / 16], x, acc[e][r]);
+                    }
+                }
+#pragma unroll
+            for (int e = 0; e < CG; ++e)
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    const int m = (c0 + e) * DS + 2 * r;
+                    *tl.template at<float2>(h, pool_bits(E[D + m])) = make_float2(acc[e][r][0], acc[e][r][1]);
+                    *tl.template at<float2>(h, pool_bits(E[D + m + 1])) = make_float2(acc[e][r][2], acc[e][r][3]);
+                }
         }
     }
 }
@@ -890,8 +998,8 @@ __device__ __forceinline__ void bdiag_mfma_block(float2 *tile, int T, const Bloc
 // narrow monomial blocks keep their wave-uniform scalar loads from the pool.
 // PG: rotation groups and coefficient forms compiled in (the single-state pass
 // kernel); the batch kernel leaves them out to keep its register budget.
-template <typename R, bool WIDE, bool CL = false, int NT = TT, bool PG = true>
-__device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, const BlockDev *bd,
+template <typename R, bool WIDE, bool CL = false, int NT = TT, bool PG = true, typename TL>
+__device__ __forceinline__ void apply_block(TL tile, int T, const BlockDev *bd,
                                             const R *__restrict__ pool, uint64_t gbase, const R *cst = nullptr,
                                             int cl_off = 0) {
     const int k = bd->k;
@@ -913,7 +1021,9 @@ __device__ __forceinline__ void apply_block(typename AmpOf<R>::A *tile, int T, c
     if constexpr (CL && F32) {
         if (kind == BK_BDMFMA) {
             const float *Es = cst + (bd->mat_off - cl_off);
-            bdiag_mfma_block<4, NT>(tile, T, bd, Es);
+            if (bd->sub == 3) bdiag_mfma_block<4, NT>(tile, T, bd, Es);
+            else if (bd->sub == 2) class_mfma_block<2, NT>(tile, T, bd, U, Es);
+            else class_mfma_block<1, NT>(tile, T, bd, U, Es);
             return;
         }
     }

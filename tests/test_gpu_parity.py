@@ -458,8 +458,10 @@ def _class_log_width(U, tol=1e-14):
 def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
     """Staged complex64 passes put 4-qubit blocks with classes of 8
     amplitudes on the matrix cores (16x16 real products of eight class
-    members at a time); the plan must contain such blocks and the state must
-    match the oracle."""
+    members at a time), and those with classes of 2 and 4 too (16-block 4x4
+    products with the class matrix broadcast from one lane quad); the plan
+    must contain each class width in staged passes and the state must match
+    the oracle."""
     from paper_2509_04955_amd import costmodel
 
     n = 16
@@ -472,7 +474,7 @@ def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
     try:
         f = costmodel.pass_features(plan)
         info = Q.qs_plan_info_get(plan)
-        hits = 0
+        hits = {1: 0, 2: 0, 3: 0}
         for p in range(info.n_passes):
             if f[p, 14] < 0.5:
                 continue
@@ -481,10 +483,11 @@ def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
                 qs, U, _ = Q.qs_plan_block(plan, b)
                 k = len(qs)
                 s = _class_log_width(U)
-                if k == 4 and s == 3:
-                    hits += 1
-        if family == "ucc":   # CNOT ladders with basis changes: classes of 8 in every tile size
-            assert hits > 0, "no 4-qubit blocks with classes of 8 in staged passes"
+                if k == 4 and s in hits:
+                    hits[s] += 1
+        if family == "ucc":   # CNOT ladders with basis changes: classes of 2, 4 and 8 in every tile size
+            for s, h in hits.items():
+                assert h > 0, f"no 4-qubit blocks with classes of {2 ** s} in staged passes"
     finally:
         Q.qs_plan_destroy(plan)
     psi0 = qsynth.random_state(n, seed=13)
