@@ -962,6 +962,20 @@ uint64_t resident_groups(const void *fn, int threads, size_t lds) {
     return (uint64_t)per_cu * (uint64_t)cus;
 }
 
+// A variant whose tile is the start of its dynamic LDS forms tile addresses
+// with OR and XOR, which needs the tile at LDS address 0 (the dynamic region
+// declares 128 KiB alignment): such a kernel must declare no static LDS.
+// Checked once per kernel from its code object's attributes.
+bool dynamic_tile_at_zero(const void *fn) {
+    static std::vector<std::pair<const void *, bool>> seen;
+    for (auto &e : seen)
+        if (e.first == fn) return e.second;
+    hipFuncAttributes attr{};
+    const bool ok = hipFuncGetAttributes(&attr, fn) == hipSuccess && attr.sharedSizeBytes == 0;
+    seen.emplace_back(fn, ok);
+    return ok;
+}
+
 }  // namespace
 
 int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool lds) {
@@ -1152,6 +1166,8 @@ qs_status launch_pass(qs_state_s &s, const qs_plan_s &p, const HPass &ps, int64_
     // dynamic LDS: none for the static-tile variants, else tile + norm slots + staged operands
     const size_t lds = static_tile ? 0 : (amp << ps.t) + kRedBytes + (size_t)pa.cl_len * (s.dtype == QS_C64 ? 4 : 8);
     const void *fn = k32 ? reinterpret_cast<const void *>(k32) : reinterpret_cast<const void *>(k64);
+    QS_CHECK(static_tile || dynamic_tile_at_zero(fn), QS_EDEVICE,
+             "tile kernel variant declares static LDS: its dynamic tile would not sit at LDS address 0");
     const uint64_t resident = resident_groups(fn, threads, lds);
     const dim3 grid((unsigned)std::min<uint64_t>(ntiles, std::min<uint64_t>(resident, kMaxTileGrid)));
     if (want_norm) {
