@@ -70,6 +70,7 @@ enum : int32_t {
     BK_PAULIG = 5,  // k consecutive Pauli rotations with independent X parts, one lane per coset
     BK_SKIP = 6,    // folded into the preceding group (no work, no barrier)
     BK_BDMFMA = 7,  // complex64 permuted block-diagonal, classes of 2, 4 or 8, on MFMA (staged passes)
+    BK_PERM = 8,    // k = 4 permutation (every nonzero entry 1): y[dest(c)] = x[c], no arithmetic
 };
 
 struct BlockDev {

@@ -532,6 +532,14 @@ bool monomial(const std::vector<cd> &U, int D, std::vector<int> &dest) {
     return true;
 }
 
+// every nonzero entry of the monomial U (column c's in row dest[c]) equals 1
+// (within kZeroTol: products of CNOT, X and SWAP gates are exact)
+bool unit_entries(const std::vector<cd> &U, int D, const std::vector<int> &dest) {
+    for (int c = 0; c < D; ++c)
+        if (std::abs(U[(size_t)dest[c] * D + c] - cd(1.0, 0.0)) > kZeroTol) return false;
+    return true;
+}
+
 bool structured_enabled() {
     static int v = -1;
     if (v < 0) {
@@ -875,6 +883,18 @@ void push_block(const HBlock &blk, BlockDev &d, int t, qs_dtype dt, bool lds, st
                     pool.push_back((R)u.real());
                     pool.push_back((R)u.imag());
                 }
+    } else if (kind == BK_PERM) {
+        // record: 2^k swizzled source byte offsets, then the destination of each
+        d.kind = BK_PERM;
+        d.mat_off = (int32_t)pool.size();
+        auto deposit = [&](int c) {
+            uint32_t o = 0;
+            for (int j = 0; j < d.k; ++j)
+                if ((c >> j) & 1) o |= 1u << d.pos[j];
+            return pool_entry<R>(sw(o) * 2 * (uint32_t)sizeof(R));
+        };
+        for (int c = 0; c < D; ++c) pool.push_back(deposit(c));
+        for (int c = 0; c < D; ++c) pool.push_back(deposit(dest[c]));
     } else if (kind == BK_MONO) {
         d.kind = BK_MONO;
         d.mat_off = (int32_t)pool.size();
@@ -920,6 +940,7 @@ double block_flops_per_amp(const BlockDev &d) {
     if (d.kind == BK_PAULIG) return 16.0 * d.k;
     if (d.kind == BK_SKIP) return 0.0;
     if (d.kind == BK_MONO) return 6.0;
+    if (d.kind == BK_PERM) return 0.0;
     if (d.kind == BK_BDIAG || d.kind == BK_BDMFMA) return 8.0 * (1 << d.sub);
     return 8.0 * (1 << d.k);
 }
@@ -935,6 +956,7 @@ size_t pass_operand_bytes(const std::vector<HBlock> &blocks, const HPass &ps, qs
                    : kind == BK_BDMFMA  ? (bdiag_width(blk) == 8 ? (size_t)(D / 8) * kBdPackFloats
                                                                   : 2 * (size_t)D + 64 * bdiag_width(blk))
                    : kind == BK_MONO    ? 4 * (size_t)D
+                   : kind == BK_PERM    ? 2 * (size_t)D
                    : kind == BK_MFMA  ? (k == 4 || (k == 5 && !big_staged(ps.t, dt)) ? (size_t)3 * D * D
                                                                                       : (size_t)4 * D * D)
                    : kind == BK_BDIAG ? 2 * (size_t)D + 2 * (size_t)D * bdiag_width(blk)
@@ -983,10 +1005,13 @@ int block_kind(const HBlock &b, int t, qs_dtype dt, std::vector<int> *dest, bool
     const int k = (int)b.qubits.size();
     std::vector<int> tmp;
     // 4-qubit monomial blocks go through the class path with classes of one
-    // (one lane per group, wave-uniform records); other widths keep the
-    // monomial path
-    if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp))
-        return k == 4 && bdiag_supported(4, 0, dt) ? BK_BDIAG : BK_MONO;
+    // (one lane per group, wave-uniform records), or as a pure permutation
+    // when every entry is 1 (CNOT ladders: no arithmetic at all); other
+    // widths keep the monomial path
+    if (structured_enabled() && monomial(b.U, 1 << k, dest ? *dest : tmp)) {
+        if (k != 4 || !bdiag_supported(4, 0, dt)) return BK_MONO;
+        return unit_entries(b.U, 1 << k, dest ? *dest : tmp) ? BK_PERM : BK_BDIAG;
+    }
     // permuted block-diagonal: 2^s complex multiply-adds per amplitude on the
     // vector ALU instead of a dense product
     int sub = 0;

@@ -41,7 +41,7 @@ void pass_features(int n, qs_dtype dt, const HPass &ps, const std::vector<HBlock
         } else if (kind == BK_PAULI) {
             ++nbd;
             flops += 16.0;
-        } else if (kind == BK_BDIAG || kind == BK_BDMFMA) {
+        } else if (kind == BK_BDIAG || kind == BK_BDMFMA || kind == BK_PERM) {
             ++nbd;
             flops += 8.0 * (1 << bdiag_log_width(blk));
         } else if (kind == BK_MFMA) {

@@ -364,6 +364,32 @@ __device__ __forceinline__ void bdiag_block(TL tl, int T, const BlockDev *bd, co
     }
 }
 
+// ---- permutation block ------------------------------------------------------
+// y[dest(c)] = x[c] with every nonzero entry 1 (products of CNOT, X, SWAP):
+// the class path without its multiplies.  Record: 2^K swizzled source byte
+// offsets, then dest(c)'s for c = 0..2^K-1 (bit patterns, wave-uniform).  A
+// lane reads its whole group before writing it.
+template <int K, typename R, int NT = TT, typename TL>
+__device__ __forceinline__ void perm_block(TL tl, int T, const BlockDev *bd, const R *__restrict__ E) {
+    using A = typename AmpOf<R>::A;
+    constexpr int D = 1 << K;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = bd->pos[j];
+    const uint32_t G = 1u << (T - K);
+    for (uint32_t g = threadIdx.x; g < G; g += NT) {
+        uint32_t b = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) b = ins0_32(b, pos[j]);
+        const uint32_t h = tl.grp(sw(b) * (uint32_t)sizeof(A));
+        A v[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c] = *tl.template at<A>(h, pool_bits(E[c]));
+#pragma unroll
+        for (int c = 0; c < D; ++c) *tl.template at<A>(h, pool_bits(E[D + c])) = v[c];
+    }
+}
+
 // One Pauli-rotation pair update: y0 = c a + sigma1 d b, y1 = c b + sigma0 d a,
 // sigma as float sign bits s0, s1.  MODE 0: c, d complex; 1: c real, d = i*dI
 // (Pauli exponentials without a phase: 4 products per output instead of 8);
@@ -1046,6 +1072,10 @@ __device__ __forceinline__ void apply_block(TL tile, int T, const BlockDev *bd,
             else if constexpr (F32) mfma_block<6, R, NT>(tile, T, bd, U);
             return;
         }
+    }
+    if (kind == BK_PERM) {
+        perm_block<4, R, NT>(tile, T, bd, U);
+        return;
     }
     if (kind == BK_BDIAG) {
         // class widths 1 <= S < K, K = 3, 4; S = 0 for K = 4 monomial blocks

@@ -498,6 +498,39 @@ def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("t", [11, 12, 13])
+def test_permutation_blocks(Q, oracle, dtype, t):
+    """4-qubit blocks whose every nonzero entry is 1 (products of CNOT, X and
+    SWAP) are applied as pure permutations (reads and permuted writes, no
+    arithmetic); the plan must contain such blocks and the state must match
+    the oracle exactly up to the state's own rounding."""
+    if dtype == 1 and t > 12:
+        pytest.skip("complex128 tiles stop at t = 12")
+    n = 16
+    c = qsynth.random_circuit(n, 500, seed=70 + t, kinds=["cx", "cx", "x", "swap"])
+    plan = Q.qs_contract(n, Q.GateList(c), Q.opts(k_max=4, tile_qubits=t, low_qubits=4))
+    try:
+        info = Q.qs_plan_info_get(plan)
+        perms = 0
+        for b in range(info.n_blocks):
+            qs, U, _ = Q.qs_plan_block(plan, b)
+            U = np.asarray(U)
+            nz = np.abs(U) > 1e-14
+            if len(qs) == 4 and (nz.sum(0) == 1).all() and np.allclose(U[nz], 1.0):
+                perms += 1
+        assert perms > 0, "no 4-qubit permutation blocks in the plan"
+    finally:
+        Q.qs_plan_destroy(plan)
+    psi0 = qsynth.random_state(n, seed=17)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=4, tile_qubits=t, low_qubits=4)
+    # a permutation moves amplitudes without arithmetic: the only error is the
+    # complex64 rounding of the input state
+    tol = 1e-7 if dtype == 0 else 1e-15
+    assert oracle.max_abs(ref, got) <= tol
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("family", ["qft", "qaoa", "phase"])
 @pytest.mark.parametrize("k_max,t", [(3, 12), (4, 13), (5, 12)])
 def test_commute_plans_match_oracle(Q, oracle, dtype, family, k_max, t):
