@@ -322,12 +322,23 @@ __global__ __launch_bounds__(NT, (tile_waves<R, WIDE, NJ, CL, NT>())) void k_til
     }
 }
 
-// one workgroup: fixed-order FP64 sum of the partials; slot[0] = N, slot[1] = 1/sqrt(N)
+// one workgroup: fixed-order FP64 sum of the partials; slot[0] = N, slot[1] = 1/sqrt(N).
+// Each thread takes eight independent loads per round (partials i + u 1024,
+// u = 0..7) and adds them pairwise in a fixed order: the loads overlap (one
+// dependent load per step took 33 us for 2^17 partials) and the result does
+// not depend on timing.
 __global__ __launch_bounds__(1024) void k_norm_reduce(const double *__restrict__ parts, uint64_t n,
                                                       double *__restrict__ slots) {
     __shared__ double sh[1024];
     double s = 0;
-    for (uint64_t i = threadIdx.x; i < n; i += 1024) s += parts[i];
+    uint64_t i = threadIdx.x;
+    for (; i + 7 * 1024 < n; i += 8 * 1024) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = parts[i + (uint64_t)u * 1024];
+        s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+    for (; i < n; i += 1024) s += parts[i];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
