@@ -99,12 +99,13 @@ __host__ __device__ __forceinline__ uint32_t sw(uint32_t li) { return li ^ (((li
 // ---- tile references ---------------------------------------------------------
 // Block code names an LDS amplitude by a group handle and an in-group byte
 // offset: grp(g) for a group whose swizzled byte offset in the tile is g, and
-// at<T>(h, o) for the element at byte g ^ o (g and o on disjoint bits, so this
-// is g + o).  TileAligned is a tile at an LDS address aligned to kTileAlign,
-// above every tile size: base + (g ^ o) = (base | g) ^ o, so a group costs one
-// OR and an access one XOR (an LDS base that is only known at link time,
-// as a dynamic region's, would otherwise cost an add per access).  TilePtr
-// places a tile at any address.
+// at<T>(h, o) for the element at tile byte offset g ^ o (the group base and
+// the in-group offset are on disjoint index bits and the swizzle is linear
+// over XOR, so g ^ o is the swizzled offset of their sum).  TileAligned is a
+// tile at an LDS address aligned to kTileAlign, above every tile size, so
+// base + (g ^ o) = (base | g) ^ o: a group costs one OR and an access one XOR
+// (an LDS base that is only known at link time, as a dynamic region's, would
+// otherwise cost an add per access).  TilePtr places a tile at any address.
 typedef __attribute__((address_space(3))) unsigned char lds_u8;
 constexpr uint32_t kTileAlign = 1u << 17;
 
