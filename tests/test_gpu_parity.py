@@ -498,6 +498,45 @@ def test_class_blocks_on_matrix_cores(Q, oracle, t, family):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("k_max,t", [(5, 12), (5, 13), (6, 12), (6, 13)])
+def test_wide_monomial_blocks_in_staged_passes(Q, oracle, dtype, k_max, t):
+    """5- and 6-qubit monomial blocks (CNOT, CZ, SWAP, X and phase gates)
+    in passes whose operands are staged in LDS read their per-lane records
+    there; the plan must contain such blocks in staged passes and the state
+    must match the oracle."""
+    from paper_2509_04955_amd import costmodel
+
+    if dtype == 1 and t > 12:
+        pytest.skip("complex128 tiles stop at t = 12")
+    if dtype == 1 and k_max > 5:
+        pytest.skip("complex128 blocks stop at k = 5")
+    n = 16
+    c = qsynth.random_circuit(n, 500, seed=5, kinds=["cx", "cz", "rz", "t", "s", "x", "swap"])
+    plan = Q.qs_contract(n, Q.GateList(c), Q.opts(k_max=k_max, tile_qubits=t, low_qubits=4, dtype=dtype))
+    try:
+        f = costmodel.pass_features(plan)
+        info = Q.qs_plan_info_get(plan)
+        hits = 0
+        for p in range(info.n_passes):
+            if f[p, 14] < 0.5:
+                continue
+            _, _, b0, nb = Q.qs_plan_pass(plan, p)
+            for b in range(b0, b0 + nb):
+                qs, U, _ = Q.qs_plan_block(plan, b)
+                nz = np.abs(np.asarray(U)) > 1e-14
+                if len(qs) >= 5 and (nz.sum(0) == 1).all():
+                    hits += 1
+        if dtype == 0:
+            assert hits > 0, "no 5- or 6-qubit monomial blocks in staged passes"
+    finally:
+        Q.qs_plan_destroy(plan)
+    psi0 = qsynth.random_state(n, seed=19)
+    ref = oracle.run(c, psi0.copy())
+    got, _ = run_plan(Q, c, dtype, psi0, k_max=k_max, tile_qubits=t, low_qubits=4)
+    assert oracle.max_abs(ref, got) <= (TOL64 if dtype == 0 else TOL128)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("t", [11, 12, 13])
 def test_permutation_blocks(Q, oracle, dtype, t):
     """4-qubit blocks whose every nonzero entry is 1 (products of CNOT, X and
