@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "tile_device.h"
 
@@ -457,8 +458,16 @@ size_t lds_operand_budget(int t, qs_dtype dt) {
 bool big_staged(int t, qs_dtype dt) { return dt == QS_C64 && t == 13 && big_tiles_enabled(); }
 
 // Raise a kernel's dynamic LDS limit once per (kernel, size).
+// Per-kernel caches of launch attributes, shared by every state: one lock
+// (a lookup per pass launch is negligible beside the pass).
+std::mutex &kernel_cache_lock() {
+    static std::mutex m;
+    return m;
+}
+
 void set_lds_limit(const void *fn, size_t bytes) {
     static std::vector<std::pair<const void *, size_t>> done;
+    std::lock_guard<std::mutex> lock(kernel_cache_lock());
     for (auto &d : done)
         if (d.first == fn) {
             if (bytes > d.second) {
@@ -1001,6 +1010,7 @@ uint64_t resident_groups(const void *fn, int threads, size_t lds) {
 // Checked once per kernel from its code object's attributes.
 bool dynamic_tile_at_zero(const void *fn) {
     static std::vector<std::pair<const void *, bool>> seen;
+    std::lock_guard<std::mutex> lock(kernel_cache_lock());
     for (auto &e : seen)
         if (e.first == fn) return e.second;
     hipFuncAttributes attr{};
